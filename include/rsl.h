@@ -1,0 +1,201 @@
+/*
+ * rsl.h -- C ABI of librsl, an MI355X (gfx950) implementation of the time step
+ * of the quadrature-based relativistic lattice Boltzmann method for massless
+ * particles, R-SLB(N_Omega; Q_xi) (Ambrus & Blaga, arXiv:1612.01287).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an int status: RSL_OK (0) or a negative RSL_E*
+ *    code; rsl_last_error() then returns a thread-local message.  No C++
+ *    exception crosses this boundary.
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *    tensors on ROCm).  The caller owns all device buffers and the HIP stream
+ *    (hipStream_t passed as void*, NULL = legacy default stream).  Work is
+ *    enqueued on that stream and the call returns without synchronising;
+ *    argument validation is synchronous.
+ *  - The library owns rsl_quad handles; they are immutable after creation and
+ *    may be shared by calls on several streams of one device.
+ *  - rsl_step never allocates device memory.
+ *
+ * Distribution layout in device memory (one instance):
+ *    f[v * pitch + s],  v = k * Q_xi + j   (radial node k outer, angle node j
+ *    inner, as the velocity grouping of App. B), s = cell index 0..nz-1,
+ *    pitch = rsl_pitch(nz) >= nz elements; element type double (RSL_F64) or
+ *    float (RSL_F32).  Ghost cells are not stored: they are generated from the
+ *    boundary rule inside the kernels.  For Bjorken flow nz = 1.
+ *  f_jk is the paper's scaled population  f_jk = 2 pi T0^3 e^{pbar_k}
+ *  w_j w_k f(p_k, xi_j)  (Sec. III E, eq. fjk), so that moments are plain sums
+ *  (eq. macro_jk).
+ */
+#ifndef RSL_H
+#define RSL_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define RSL_OK            0
+#define RSL_EINVAL       (-1)  /* bad argument: sizes, states, null pointers          */
+#define RSL_EUNSUPPORTED (-2)  /* outside the model family built here                 */
+#define RSL_EUNSTABLE    (-3)  /* time step beyond the CFL or stiffness limit         */
+#define RSL_EDEVICE      (-4)  /* a HIP runtime error (message has the HIP text)      */
+#define RSL_ENONFINITE   (-5)  /* a cell reached an unphysical or non-finite state    */
+
+/* ------------------------------------------------------------ enumerations */
+#define RSL_SOD        0   /* 1D shock tube, Sec. IV, operator eq. L_Sod            */
+#define RSL_BJORKEN    1   /* 0+1D Bjorken flow, Sec. V, operator eq. L_Bjorken     */
+
+#define RSL_TAU_CONST  0   /* tau_AW = tau_r in every cell                          */
+#define RSL_TAU_ETAS   1   /* constant eta/s: tau_AW = tau_AW0 / T * (1 - ln(lambda_bar lambda_ref)/4)
+                              (eq. Sod:tau); Bjorken ideal gas eq. bjorken_tauAW_mu;
+                              parton gas tau_AW = tau_AW0 / T                     */
+#define RSL_TAU_INF    2   /* collisionless (ballistic) limit                       */
+
+#define RSL_GAS_IDEAL  0   /* P = n T, n conserved                                  */
+#define RSL_GAS_PARTON 1   /* mu = 0: T = P^{1/4}, n_eq = T^3 (Sec. V D); Bjorken only */
+
+#define RSL_BC_EQ      0   /* 3 ghost cells per side fixed to f^eq of the initial
+                              left / right states (Sec. IV A)                      */
+#define RSL_BC_OUTFLOW 1   /* zero-gradient: ghosts copy the first / last cell      */
+
+#define RSL_F64        0   /* f stored in binary64                                  */
+#define RSL_F32        1   /* f stored in binary32; all per-cell work (moments,
+                              Landau frame, tau, f^eq coefficients) stays binary64 */
+
+#define RSL_FLAG_FORCE_UNSTABLE 1  /* rsl_step: skip the stiffness guard          */
+#define RSL_QUAD_HOST_ONLY      1  /* rsl_make_quadrature: build host tables only  */
+
+/* Fields of rsl_moments output, per cell, in this order. */
+#define RSL_NMOM 13
+/* N^0, N^z, T^00, T^0z, T^zz  (eq. macro_jk)
+ * n, E, P, T, beta            (Landau frame, eqs. E_landau, u_landau; P = E/3, T = P/n)
+ * lambda_bar = n / T^3        (relative fugacity)
+ * q  = -4 T (N^z - n beta gamma)        (eq. q_val)
+ * Pi = 2E/3 - T^00 + T^zz               (eq. pi_val)
+ * For Bjorken flow (u = (1,0,0,0)): N^z = T^0z = 0 slots hold 0, T^zz holds
+ * P_L = T^{eta eta}, Pi = P_L - P, q = 0. */
+
+typedef struct rsl_quad rsl_quad;
+
+/* Problem description (Sod: Sec. IV A; Bjorken: Sec. V A).  Plain data. */
+typedef struct rsl_problem {
+    int problem;      /* RSL_SOD | RSL_BJORKEN                                      */
+    int nz;           /* cells; Sod: >= 5; Bjorken: must be 1                       */
+    int dtype;        /* RSL_F64 | RSL_F32                                          */
+    int bc;           /* RSL_BC_EQ | RSL_BC_OUTFLOW (Sod)                           */
+    int tau_mode;     /* RSL_TAU_*                                                  */
+    int gas;          /* RSL_GAS_* (Bjorken; Sod is always ideal)                   */
+    int flags;        /* RSL_FLAG_*                                                 */
+    int reserved;
+    double z_lo, z_hi;        /* Sod domain, cell centres z_s = z_lo + (s + 1/2) dz    */
+    double n_L, T_L;          /* Sod left state at rest; Bjorken initial state at tau0 */
+    double n_R, T_R;          /* Sod right state at rest                               */
+    double tau_r;             /* RSL_TAU_CONST relaxation time                          */
+    double tau_aw0;           /* RSL_TAU_ETAS: tau_{A-W;0}                              */
+    double lambda_ref;        /* RSL_TAU_ETAS: lambda_ref (1 in the paper's setups)     */
+    double kappa;             /* stiffness guard dt <= kappa * tau_min (0 -> 2.0)       */
+} rsl_problem;
+
+/* Build the velocity set R-SLB(N_Omega; Q_xi) with Q_L radial nodes
+ * (Sec. III E): Gauss-Legendre nodes/weights in xi = cos(theta) (eq. quad_xi),
+ * generalised Gauss-Laguerre (alpha = 2) radial nodes p_k = T0 pbar_k and
+ * weights (eq. wL, Table I), Legendre tables P_m(xi_j), the momentum-space
+ * kernels K^L (eq. K_lag_disc) and K^P (eq. K_leg_disc), and the tables the
+ * kernels use for the equilibrium coefficients (Sec. III D, eq. feq_trunc).
+ * Tables are built in host extended precision and uploaded to the current
+ * HIP device unless flags has RSL_QUAD_HOST_ONLY.
+ * Limits: 2 <= Q_L <= 8, N_L = 1, 0 <= N_Omega <= 6, N_Omega < Q_xi <= 1024,
+ * T0 > 0.  Errors: RSL_EINVAL, RSL_EUNSUPPORTED (N_L != 1, N_Omega > 6),
+ * RSL_EDEVICE.  *out is NULL on error. */
+int rsl_make_quadrature(int Q_L, int Q_xi, int N_L, int N_Omega, double T0, int flags,
+                        rsl_quad** out);
+void rsl_free_quadrature(rsl_quad* q);
+
+/* Host copies of the tables, for inspection.  which: */
+#define RSL_TAB_XI   0   /* xi_j,      Q_xi values, ascending                         */
+#define RSL_TAB_WXI  1   /* w_j,       Q_xi values                                    */
+#define RSL_TAB_PBAR 2   /* pbar_k,    Q_L values, ascending                          */
+#define RSL_TAB_WL   3   /* w_k,       Q_L values                                     */
+#define RSL_TAB_KL   4   /* K^L_{k,k'}, Q_L x Q_L row-major                           */
+#define RSL_TAB_KP   5   /* K^P_{j,j'}, Q_xi x Q_xi row-major                          */
+/* Copies up to n doubles; *count (if not NULL) receives the table length. */
+int rsl_quad_table(const rsl_quad* q, int which, double* host_out, int n, int* count);
+
+/* Elements per velocity plane for nz cells (multiple of 64, >= nz). */
+int rsl_pitch(int nz);
+
+/* Sizes of the caller-owned buffers for one instance: f (the state) and work
+ * (two RK stage copies of f, the boundary states and a status word). */
+int rsl_sizes(const rsl_quad* q, const rsl_problem* p, size_t* f_bytes, size_t* work_bytes);
+
+/* Initial state.  Sod: f = f^eq(n_L, T_L, u = 0) for z_s < centre and
+ * f^eq(n_R, T_R, 0) beyond, the cell centred on the membrane (odd nz) taking
+ * the mean (Sec. IV A); the f^eq used is the truncated expansion at the nodes.
+ * Bjorken: f = f^eq(n_L, T_L, 0) (eq. bjorken_f0 with n_L = T_L = 1).
+ * Also clears the status word in work. */
+int rsl_init(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_dev,
+             void* hip_stream);
+
+/* Advance f by nsteps steps of the TVD RK3 scheme (eq. rk3, stage times of
+ * Table II) applied to L_Sod (eq. L_Sod: WENO5 advection, Sec. III F, plus the
+ * Anderson-Witting term) or L_Bjorken (eq. L_Bjorken).  *t (host) is the
+ * time (Sod) or proper time tau (Bjorken) and advances by nsteps*dt.
+ * Errors: RSL_EINVAL; RSL_EUNSTABLE if dt*max|xi|/dz >= 1 (CFL, eq. CFL) or
+ * dt > kappa * tau_min at the initial states, unless RSL_FLAG_FORCE_UNSTABLE.
+ * Unphysical cell states are reported by the next rsl_moments / rsl_status. */
+int rsl_step(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_dev,
+             double* t, double dt, int nsteps, void* hip_stream);
+
+/* Per-cell fields (RSL_NMOM doubles per cell, cell-major: out[s*13 + field])
+ * written to out_dev on the stream.  Bjorken writes one row. */
+int rsl_moments(const rsl_quad* q, const rsl_problem* p, const void* f_dev, void* work_dev,
+                double* out_dev, void* hip_stream);
+
+/* Synchronises the stream and reads the status word: RSL_OK, or
+ * RSL_ENONFINITE if any kernel since rsl_init met an unphysical state. */
+int rsl_status(const rsl_quad* q, const rsl_problem* p, void* work_dev, void* hip_stream);
+
+const char* rsl_last_error(void);
+
+/* ---------------------------------------------------------------- batches
+ * Many instances of one problem kind and one dtype, of uneven nz, velocity
+ * set and relaxation law, advanced together.  Sod batches run one launch per
+ * RK stage for all instances (work items = (instance, 63-cell tile), ordered
+ * per XCD, costliest first); Bjorken batches run one launch per call (one
+ * workgroup per instance, all steps inside).  Each instance has its own time
+ * step dt[i].  The batch copies the problem structs and keeps pointers to the
+ * quads, which must outlive it.  Device memory of the batch (descriptor and
+ * work-item tables) is allocated at creation; stepping allocates nothing and
+ * may be captured into a HIP graph.
+ * Buffers: one f buffer and one work buffer for the whole batch
+ * (rsl_batch_sizes); instance i's f starts rsl_batch_offset(i) bytes into f,
+ * with the single-instance layout. */
+typedef struct rsl_batch rsl_batch;
+int rsl_batch_create(const rsl_quad* const* quads, const rsl_problem* problems, const double* dt, int n,
+                     rsl_batch** out);
+void rsl_batch_free(rsl_batch* b);
+int rsl_batch_sizes(const rsl_batch* b, size_t* f_bytes, size_t* work_bytes);
+int rsl_batch_offset(const rsl_batch* b, int i, size_t* f_offset);
+/* Host-side time of instance i (advanced by rsl_batch_step). */
+int rsl_batch_time(const rsl_batch* b, int i, double* t);
+int rsl_batch_init(rsl_batch* b, void* f_dev, void* work_dev, void* hip_stream);
+/* nsteps RK3 steps of every instance (eq. rk3 with L_Sod or L_Bjorken). */
+int rsl_batch_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream);
+/* One RK3 stage (1, 2 or 3) of every Sod instance, without advancing the
+ * host-side times: stage s reads f_n and the stage field s-1 and writes stage
+ * field s (stage 3 writes f_{n+1} over f_n).  For custom drivers and timing. */
+int rsl_batch_stage(rsl_batch* b, void* f_dev, void* work_dev, int stage, void* hip_stream);
+/* Per-cell fields of every instance, rows concatenated in instance order
+ * (nz rows per Sod instance, one per Bjorken instance), RSL_NMOM per row. */
+int rsl_batch_moments(rsl_batch* b, const void* f_dev, void* work_dev, double* out_dev, void* hip_stream);
+/* Synchronises and reads every instance's status word; *first_bad (if not
+ * NULL) receives the first failing instance or -1. */
+int rsl_batch_status(rsl_batch* b, void* work_dev, void* hip_stream, int* first_bad);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSL_H */

@@ -1,0 +1,288 @@
+// C ABI of librsl: argument validation, table upload, kernel sequencing.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "rsl_impl.h"
+
+namespace rsl {
+
+int build_quadrature(int QL, int Q, int NOm, double T0, rsl_quad* q);
+
+namespace {
+thread_local std::string g_err;
+}
+
+int set_error(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return RSL_OK;
+    return set_error(RSL_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+WorkLayout work_layout(const rsl_quad* q, const rsl_problem* p) {
+    WorkLayout L{};
+    const size_t es = p->dtype == RSL_F32 ? 4 : 8;
+    const size_t pitch = p->problem == RSL_SOD ? (size_t)rsl_pitch(p->nz) : 1;
+    L.f_bytes = align_up(es * pitch * q->V, 256);
+    L.f1_off = 0;
+    L.f2_off = L.f_bytes;
+    L.feqL_off = 2 * L.f_bytes;
+    L.feqR_off = L.feqL_off + align_up(sizeof(double) * q->V, 256);
+    L.status_off = L.feqR_off + align_up(sizeof(double) * q->V, 256);
+    L.total = L.status_off + 256;
+    return L;
+}
+
+InstDesc make_desc(const rsl_quad* q, const rsl_problem* p, void* f, void* work, double dt) {
+    InstDesc d{};
+    const WorkLayout L = work_layout(q, p);
+    d.nz = p->problem == RSL_SOD ? p->nz : 1;
+    d.pitch = p->problem == RSL_SOD ? rsl_pitch(p->nz) : 1;
+    d.Q = q->Q;
+    d.QL = q->QL;
+    d.V = q->V;
+    d.NOm = q->NOm;
+    d.bc = p->bc;
+    d.tau_mode = p->tau_mode;
+    d.gas = p->gas;
+    d.dtype = p->dtype;
+    d.dz = p->problem == RSL_SOD ? (p->z_hi - p->z_lo) / p->nz : 1.0;
+    d.dz_inv = 1.0 / d.dz;
+    d.z_lo = p->z_lo;
+    d.dt = dt;
+    d.tau_r = p->tau_r;
+    d.tau_aw0 = p->tau_aw0;
+    d.lambda_ref = p->lambda_ref > 0 ? p->lambda_ref : 1.0;
+    d.T0 = q->T0;
+    d.beta_series = q->beta_series;
+    d.tab = q->dev;
+    char* w = (char*)work;
+    d.f = f;
+    d.f1 = w + L.f1_off;
+    d.f2 = w + L.f2_off;
+    d.feqL = (const double*)(w + L.feqL_off);
+    d.feqR = (const double*)(w + L.feqR_off);
+    d.status = (unsigned*)(w + L.status_off);
+    d.clock = (double*)(w + L.status_off + 8);
+    return d;
+}
+
+}  // namespace rsl
+
+using namespace rsl;
+
+namespace {
+
+int check_quad(const rsl_quad* q) {
+    if (!q) return set_error(RSL_EINVAL, "null rsl_quad");
+    if (!q->on_device) return set_error(RSL_EINVAL, "rsl_quad was built with RSL_QUAD_HOST_ONLY");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != q->device)
+        return set_error(RSL_EINVAL, "rsl_quad belongs to another HIP device than the current one");
+    return RSL_OK;
+}
+
+bool pos(double x) { return x > 0.0 && std::isfinite(x); }
+
+int check_problem(const rsl_quad* q, const rsl_problem* p) {
+    if (!p) return set_error(RSL_EINVAL, "null rsl_problem");
+    if (p->problem != RSL_SOD && p->problem != RSL_BJORKEN) return set_error(RSL_EINVAL, "unknown problem kind");
+    if (p->dtype != RSL_F64 && p->dtype != RSL_F32) return set_error(RSL_EINVAL, "dtype must be RSL_F64 or RSL_F32");
+    if (p->tau_mode < RSL_TAU_CONST || p->tau_mode > RSL_TAU_INF) return set_error(RSL_EINVAL, "unknown tau_mode");
+    if (p->tau_mode == RSL_TAU_CONST && !pos(p->tau_r)) return set_error(RSL_EINVAL, "tau_r must be > 0");
+    if (p->tau_mode == RSL_TAU_ETAS && !pos(p->tau_aw0)) return set_error(RSL_EINVAL, "tau_aw0 must be > 0");
+    if (!pos(p->n_L) || !pos(p->T_L)) return set_error(RSL_EINVAL, "left/initial state needs n > 0, T > 0");
+    if (p->problem == RSL_SOD) {
+        if (p->nz < 5 || p->nz > (1 << 28)) return set_error(RSL_EINVAL, "Sod needs 5 <= nz <= 2^28");
+        if (!(p->z_hi > p->z_lo)) return set_error(RSL_EINVAL, "Sod needs z_hi > z_lo");
+        if (!pos(p->n_R) || !pos(p->T_R)) return set_error(RSL_EINVAL, "right state needs n > 0, T > 0");
+        if (p->bc != RSL_BC_EQ && p->bc != RSL_BC_OUTFLOW) return set_error(RSL_EINVAL, "unknown bc");
+        if (p->gas != RSL_GAS_IDEAL) return set_error(RSL_EUNSUPPORTED, "the Sod problem is built for the ideal gas");
+    } else {
+        if (p->nz != 1) return set_error(RSL_EINVAL, "Bjorken flow needs nz = 1");
+        if (p->gas != RSL_GAS_IDEAL && p->gas != RSL_GAS_PARTON) return set_error(RSL_EINVAL, "unknown gas");
+    }
+    (void)q;
+    return RSL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rsl_last_error(void) { return g_err.c_str(); }
+
+int rsl_pitch(int nz) { return nz <= 0 ? 0 : (nz + 63) / 64 * 64; }
+
+int rsl_make_quadrature(int Q_L, int Q_xi, int N_L, int N_Omega, double T0, int flags, rsl_quad** out) {
+    if (!out) return set_error(RSL_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (N_L != 1) return set_error(RSL_EUNSUPPORTED, "only N_L = 1 is built (the paper's radial truncation)");
+    if (N_Omega > kMaxNOm) return set_error(RSL_EUNSUPPORTED, "N_Omega > 6: no equilibrium coefficients (App. A)");
+    if (Q_L < 2 || Q_L > 8) return set_error(RSL_EINVAL, "need 2 <= Q_L <= 8");
+    if (N_Omega < 0 || Q_xi <= N_Omega || Q_xi > 1024) return set_error(RSL_EINVAL, "need 0 <= N_Omega < Q_xi <= 1024");
+    if (!pos(T0)) return set_error(RSL_EINVAL, "T0 must be > 0");
+    rsl_quad* q = new (std::nothrow) rsl_quad();
+    if (!q) return set_error(RSL_EINVAL, "out of host memory");
+    int rc = build_quadrature(Q_L, Q_xi, N_Omega, T0, q);
+    if (rc != RSL_OK) { delete q; return rc; }
+    if (!(flags & RSL_QUAD_HOST_ONLY)) {
+        const int V = q->V, Q = q->Q, QL = q->QL;
+        std::vector<double> wxw(V), pk(QL), L1(QL);
+        for (int k = 0; k < QL; ++k) {
+            pk[k] = T0 * q->pbar[k];
+            L1[k] = 3.0 - q->pbar[k];
+            for (int j = 0; j < Q; ++j) wxw[k * Q + j] = q->wxi[j] * q->wL[k];
+        }
+        const std::vector<double>* parts[] = {&q->xi, &wxw, &pk, &L1, &q->Pm, &q->ser, &q->thr, &q->KL, &q->KP};
+        size_t off[9], total = 0;
+        for (int i = 0; i < 9; ++i) {
+            off[i] = total;
+            total += align_up(parts[i]->size() * sizeof(double), 256);
+        }
+        if ((rc = hip_check(hipGetDevice(&q->device), "hipGetDevice")) != RSL_OK) { delete q; return rc; }
+        if ((rc = hip_check(hipMalloc(&q->dmem, total), "hipMalloc(tables)")) != RSL_OK) { delete q; return rc; }
+        std::vector<char> host(total, 0);
+        for (int i = 0; i < 9; ++i) std::memcpy(host.data() + off[i], parts[i]->data(), parts[i]->size() * sizeof(double));
+        rc = hip_check(hipMemcpy(q->dmem, host.data(), total, hipMemcpyHostToDevice), "hipMemcpy(tables)");
+        if (rc != RSL_OK) { (void)hipFree(q->dmem); delete q; return rc; }
+        char* b = (char*)q->dmem;
+        q->dev.xi = (const double*)(b + off[0]);
+        q->dev.wxw = (const double*)(b + off[1]);
+        q->dev.pk = (const double*)(b + off[2]);
+        q->dev.L1 = (const double*)(b + off[3]);
+        q->dev.Pm = (const double*)(b + off[4]);
+        q->dev.ser = (const double*)(b + off[5]);
+        q->dev.thr = (const double*)(b + off[6]);
+        q->dev.KL = (const double*)(b + off[7]);
+        q->dev.KP = (const double*)(b + off[8]);
+        q->on_device = true;
+    }
+    *out = q;
+    return RSL_OK;
+}
+
+void rsl_free_quadrature(rsl_quad* q) {
+    if (!q) return;
+    if (q->dmem) (void)hipFree(q->dmem);
+    delete q;
+}
+
+int rsl_quad_table(const rsl_quad* q, int which, double* host_out, int n, int* count) {
+    if (!q) return set_error(RSL_EINVAL, "null rsl_quad");
+    const std::vector<double>* t = nullptr;
+    switch (which) {
+        case RSL_TAB_XI: t = &q->xi; break;
+        case RSL_TAB_WXI: t = &q->wxi; break;
+        case RSL_TAB_PBAR: t = &q->pbar; break;
+        case RSL_TAB_WL: t = &q->wL; break;
+        case RSL_TAB_KL: t = &q->KL; break;
+        case RSL_TAB_KP: t = &q->KP; break;
+        default: return set_error(RSL_EINVAL, "unknown table");
+    }
+    if (count) *count = (int)t->size();
+    if (host_out && n > 0) std::memcpy(host_out, t->data(), sizeof(double) * std::min((size_t)n, t->size()));
+    return RSL_OK;
+}
+
+int rsl_sizes(const rsl_quad* q, const rsl_problem* p, size_t* f_bytes, size_t* work_bytes) {
+    if (!q) return set_error(RSL_EINVAL, "null rsl_quad");
+    int rc = check_problem(q, p);
+    if (rc) return rc;
+    const WorkLayout L = work_layout(q, p);
+    if (f_bytes) *f_bytes = L.f_bytes;
+    if (work_bytes) *work_bytes = L.total;
+    return RSL_OK;
+}
+
+int rsl_init(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_dev, void* hip_stream) {
+    int rc = check_quad(q);
+    if (rc || (rc = check_problem(q, p))) return rc;
+    if (!f_dev || !work_dev) return set_error(RSL_EINVAL, "null device buffer");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const WorkLayout L = work_layout(q, p);
+    InstDesc d = make_desc(q, p, f_dev, work_dev, 0.0);
+    if ((rc = hip_check(hipMemsetAsync((char*)work_dev + L.status_off, 0, 256, s), "clear status"))) return rc;
+    if (p->problem == RSL_SOD) {
+        if ((rc = launch_boundary_states(d, p->n_L, p->T_L, p->n_R, p->T_R, s))) return rc;
+        return launch_sod_init(d, s);
+    }
+    return launch_bj_init(d, p->n_L, p->T_L, 1.0, s);
+}
+
+int rsl_step(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_dev, double* t, double dt,
+             int nsteps, void* hip_stream) {
+    int rc = check_quad(q);
+    if (rc || (rc = check_problem(q, p))) return rc;
+    if (!f_dev || !work_dev || !t) return set_error(RSL_EINVAL, "null argument");
+    if (nsteps < 0) return set_error(RSL_EINVAL, "nsteps < 0");
+    if (!pos(dt)) return set_error(RSL_EINVAL, "dt must be > 0");
+    const double kappa = p->kappa > 0 ? p->kappa : 2.0;
+    const bool force = p->flags & RSL_FLAG_FORCE_UNSTABLE;
+    if (p->problem == RSL_SOD) {
+        const double dz = (p->z_hi - p->z_lo) / p->nz;
+        const double vmax = std::fabs(q->xi.back());
+        if (dt * vmax / dz >= 1.0 && !force)
+            return set_error(RSL_EUNSTABLE, "CFL number dt*max|xi|/dz >= 1");
+    }
+    if (p->tau_mode != RSL_TAU_INF && !force) {
+        double tmin = p->tau_r;
+        if (p->tau_mode == RSL_TAU_ETAS) {
+            auto tau_of = [&](double n, double T) {
+                return p->tau_aw0 / T * (1.0 - 0.25 * std::log(n / (T * T * T) * (p->lambda_ref > 0 ? p->lambda_ref : 1.0)));
+            };
+            tmin = tau_of(p->n_L, p->T_L);
+            if (p->problem == RSL_SOD) tmin = std::min(tmin, tau_of(p->n_R, p->T_R));
+        }
+        if (!(dt <= kappa * tmin))
+            return set_error(RSL_EUNSTABLE, "dt exceeds kappa * tau_AW (stiff relaxation); set RSL_FLAG_FORCE_UNSTABLE to override");
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    InstDesc d = make_desc(q, p, f_dev, work_dev, dt);
+    if (p->problem == RSL_SOD) {
+        for (int it = 0; it < nsteps; ++it)
+            for (int st = 1; st <= 3; ++st)
+                if ((rc = launch_sod_stage(d, st, s))) return rc;
+    } else if (nsteps > 0) {
+        if ((rc = launch_bj_steps(d, *t, dt, nsteps, s))) return rc;
+    }
+    *t += nsteps * dt;
+    return RSL_OK;
+}
+
+int rsl_moments(const rsl_quad* q, const rsl_problem* p, const void* f_dev, void* work_dev, double* out_dev,
+                void* hip_stream) {
+    int rc = check_quad(q);
+    if (rc || (rc = check_problem(q, p))) return rc;
+    if (!f_dev || !work_dev || !out_dev) return set_error(RSL_EINVAL, "null device buffer");
+    InstDesc d = make_desc(q, p, (void*)f_dev, work_dev, 0.0);
+    if (p->problem == RSL_SOD) return launch_sod_moments(d, f_dev, out_dev, (hipStream_t)hip_stream);
+    return launch_bj_moments(d, f_dev, out_dev, (hipStream_t)hip_stream);
+}
+
+int rsl_status(const rsl_quad* q, const rsl_problem* p, void* work_dev, void* hip_stream) {
+    int rc = check_quad(q);
+    if (rc || (rc = check_problem(q, p))) return rc;
+    if (!work_dev) return set_error(RSL_EINVAL, "null work buffer");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
+    unsigned word = 0;
+    const WorkLayout L = work_layout(q, p);
+    if ((rc = hip_check(hipMemcpy(&word, (char*)work_dev + L.status_off, sizeof(word), hipMemcpyDeviceToHost),
+                        "read status")))
+        return rc;
+    if (word & 1u) return set_error(RSL_ENONFINITE, "a cell reached an unphysical state (Landau frame undefined)");
+    if (word & 2u) return set_error(RSL_ENONFINITE, "a population became non-finite");
+    return RSL_OK;
+}
+
+}  // extern "C"

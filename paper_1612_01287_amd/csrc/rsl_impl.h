@@ -1,0 +1,119 @@
+// Internal definitions shared by the host side and the kernels of librsl.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rsl.h"
+
+namespace rsl {
+
+// Largest N_Omega with equilibrium coefficients (App. A gives m <= 6).
+constexpr int kMaxNOm = 6;
+// Terms kept in the Maclaurin tables of K_{3,m}, K_{4,m} (see rsl_math.h).
+constexpr int kSeriesTerms = 128;
+// Cells per wavefront tile: 64 lanes carry 64 interface fluxes, 63 cells are updated.
+constexpr int kLanes = 64;
+constexpr int kTileCells = kLanes - 1;
+// LDS window per velocity plane: cells z0-3 .. z0+65 (69 values), padded.
+constexpr int kWin = 72;
+
+// Device-side tables of one velocity set.  All pointers are device memory
+// owned by the rsl_quad that carries this struct.
+struct QuadDev {
+    const double* xi;    // [Q]      Gauss-Legendre nodes
+    const double* wxw;   // [V]      w_j * w_k, v = k*Q + j
+    const double* pk;    // [QL]     p_k = T0 * pbar_k
+    const double* L1;    // [QL]     L_1^(2)(pbar_k) = 3 - pbar_k
+    const double* Pm;    // [(NOm+1)*Q]  P_m(xi_j), row m
+    const double* ser;   // [2][kMaxNOm+1][kSeriesTerms]  Maclaurin coefficients of K_{3,m}, K_{4,m}
+    const double* thr;   // [kSeriesTerms]  beta^2 below which i terms suffice
+    const double* KL;    // [QL*QL]
+    const double* KP;    // [Q*Q]
+};
+
+// Everything a kernel needs about one problem instance.  Passed by value as a
+// kernel argument for single-instance calls and stored in device arrays by
+// the batched path.
+struct InstDesc {
+    int nz, pitch, Q, QL, V, NOm, bc, tau_mode;
+    int gas, dtype, pad0, pad1;
+    double dz_inv, dt, tau_r, tau_aw0, lambda_ref, T0, beta_series;
+    double z_lo, dz;
+    QuadDev tab;
+    void* f;             // state  f_n       [V][pitch]
+    void* f1;            // stage  f^(1)
+    void* f2;            // stage  f^(2)
+    const double* feqL;  // [V] ghost state left  (RSL_BC_EQ)
+    const double* feqR;  // [V] ghost state right
+    unsigned* status;    // bit 0: unphysical cell state; bit 1: non-finite f
+    double* clock;       // Bjorken batches: current proper time of the instance
+};
+
+// Descriptors stored by a batch hold byte offsets (f relative to the batch's f
+// buffer, the rest relative to its work buffer); kernels add the bases.
+__host__ __device__ inline void rebase(InstDesc& d, char* fbase, char* wbase) {
+    d.f = fbase + (size_t)d.f;
+    d.f1 = wbase + (size_t)d.f1;
+    d.f2 = wbase + (size_t)d.f2;
+    d.feqL = (const double*)(wbase + (size_t)d.feqL);
+    d.feqR = (const double*)(wbase + (size_t)d.feqR);
+    d.status = (unsigned*)(wbase + (size_t)d.status);
+    d.clock = (double*)(wbase + (size_t)d.clock);
+}
+
+// One batched launch: device descriptor table and work-item list.
+struct BatchLaunch {
+    const InstDesc* descs;   // device [n]
+    const int2* items;       // device [nitems], (instance, tile) or (-1, -1)
+    int nitems;
+    int stash_limit;         // bytes of LDS window allowed per workgroup
+    size_t lds_bytes;        // dynamic LDS of the launch
+};
+
+}  // namespace rsl
+
+struct rsl_quad {
+    int QL, Q, NOm, V;
+    double T0;
+    double beta_series;        // |beta| below which the Maclaurin branch is used
+    std::vector<double> xi, wxi, pbar, wL, KL, KP, Pm, ser, thr;
+    bool on_device = false;
+    int device = -1;
+    void* dmem = nullptr;      // one allocation holding every table
+    rsl::QuadDev dev{};
+};
+
+namespace rsl {
+
+int set_error(int code, const std::string& msg);
+int hip_check(hipError_t e, const char* what);
+
+// Work-buffer layout for one instance.
+struct WorkLayout {
+    size_t f_bytes, f1_off, f2_off, feqL_off, feqR_off, status_off, total;
+};
+WorkLayout work_layout(const rsl_quad* q, const rsl_problem* p);
+InstDesc make_desc(const rsl_quad* q, const rsl_problem* p, void* f, void* work, double dt);
+
+// Kernel launchers (sod.hip, bjorken.hip).
+int launch_boundary_states(const InstDesc& d, double nL, double TL, double nR, double TR,
+                           hipStream_t s);
+int launch_sod_init(const InstDesc& d, hipStream_t s);
+int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s);
+int launch_sod_moments(const InstDesc& d, const void* f, double* out, hipStream_t s);
+int launch_sod_batch_stage(const BatchLaunch& b, int dtype, int stage, char* fbase, char* wbase, hipStream_t s);
+size_t sod_red_bytes();
+size_t sod_max_lds();
+int launch_bj_batch_steps(const InstDesc* descs, int n, size_t lds, int dtype, char* fbase, char* wbase,
+                          double tau0, double dtau, int nsteps, hipStream_t s);
+int launch_bj_init(const InstDesc& d, double n0, double T0s, double tau0, hipStream_t s);
+size_t bj_lds_bytes(int V);
+int launch_bj_steps(const InstDesc& d, double tau0, double dtau, int nsteps, hipStream_t s);
+int launch_bj_moments(const InstDesc& d, const void* f, double* out, hipStream_t s);
+
+}  // namespace rsl

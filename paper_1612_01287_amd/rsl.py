@@ -1,0 +1,280 @@
+"""ctypes binding of librsl (include/rsl.h) with torch tensors as device memory.
+
+Argument marshalling only: every step of the R-SLB path runs in the HIP
+kernels of librsl.so.  The library must have been built (``build.py``); a
+missing library raises at import, there is no fallback.
+"""
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librsl.so")
+HEADER = os.path.join(HERE, "..", "include", "rsl.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("librsl.so is not built: run `python -m paper_1612_01287_amd.build` "
+                      "(or __graft_entry__.build()) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+def _constants():
+    """#define RSL_* integer constants parsed from the public header."""
+    out = {}
+    with open(HEADER) as fh:
+        for line in fh:
+            m = re.match(r"#define\s+(RSL_\w+)\s+\(?(-?\d+)\)?", line)
+            if m:
+                out[m.group(1)] = int(m.group(2))
+    return out
+
+
+C = _constants()
+globals().update(C)
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Problem(ctypes.Structure):
+    """Mirror of struct rsl_problem."""
+    _fields_ = [("problem", ctypes.c_int), ("nz", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("bc", ctypes.c_int), ("tau_mode", ctypes.c_int), ("gas", ctypes.c_int),
+                ("flags", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("z_lo", ctypes.c_double), ("z_hi", ctypes.c_double),
+                ("n_L", ctypes.c_double), ("T_L", ctypes.c_double),
+                ("n_R", ctypes.c_double), ("T_R", ctypes.c_double),
+                ("tau_r", ctypes.c_double), ("tau_aw0", ctypes.c_double),
+                ("lambda_ref", ctypes.c_double), ("kappa", ctypes.c_double)]
+
+
+def _sig(name, res, args):
+    fn = getattr(_lib, name)
+    fn.restype = res
+    fn.argtypes = args
+    return fn
+
+
+_sig("rsl_make_quadrature", ctypes.c_int,
+     [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+      ctypes.POINTER(_vp)])
+_sig("rsl_free_quadrature", None, [_vp])
+_sig("rsl_quad_table", ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)])
+_sig("rsl_pitch", ctypes.c_int, [ctypes.c_int])
+_sig("rsl_sizes", ctypes.c_int, [_vp, ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t),
+                                 ctypes.POINTER(ctypes.c_size_t)])
+_sig("rsl_init", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _vp])
+_sig("rsl_step", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _dp, ctypes.c_double,
+                                ctypes.c_int, _vp])
+_sig("rsl_moments", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _vp, _vp])
+_sig("rsl_status", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp])
+_sig("rsl_last_error", ctypes.c_char_p, [])
+
+MOMENT_FIELDS = ("N0", "Nz", "T00", "T0z", "Tzz", "n", "E", "P", "T", "beta", "lambda", "q", "Pi")
+
+
+class RslError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("rsl error %d: %s" % (code, msg))
+        self.code = code
+
+
+def check(rc):
+    if rc != 0:
+        raise RslError(rc, _lib.rsl_last_error().decode())
+    return rc
+
+
+def lib():
+    return _lib
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Quadrature:
+    """R-SLB(N_Omega; Q_xi) velocity set with Q_L radial nodes (owned library handle)."""
+
+    def __init__(self, QL, Q, NOm, T0=1.0, host_only=False):
+        h = _vp()
+        check(_lib.rsl_make_quadrature(QL, Q, 1, NOm, float(T0),
+                                       C["RSL_QUAD_HOST_ONLY"] if host_only else 0, ctypes.byref(h)))
+        self._h = h
+        self.QL, self.Q, self.NOm, self.T0 = QL, Q, NOm, float(T0)
+        self.V = QL * Q
+
+    @property
+    def handle(self):
+        return self._h
+
+    def table(self, which):
+        import numpy as np
+        cnt = ctypes.c_int(0)
+        check(_lib.rsl_quad_table(self._h, which, None, 0, ctypes.byref(cnt)))
+        out = np.zeros(cnt.value)
+        check(_lib.rsl_quad_table(self._h, which, out.ctypes.data_as(_dp), cnt.value, None))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.rsl_free_quadrature(h)
+            self._h = None
+
+
+def make_problem(kind="sod", nz=400, dtype="f64", bc="outflow", tau_mode="const", gas="ideal",
+                 z_lo=-0.5, z_hi=0.5, nL=1.0, TL=1.0, nR=0.4, TR=0.8, tau_r=1e-3, tau_aw0=0.0,
+                 lambda_ref=1.0, kappa=0.0, force=False):
+    p = Problem()
+    p.problem = C["RSL_SOD"] if kind == "sod" else C["RSL_BJORKEN"]
+    p.nz = nz if kind == "sod" else 1
+    p.dtype = C["RSL_F64"] if dtype == "f64" else C["RSL_F32"]
+    p.bc = C["RSL_BC_OUTFLOW"] if bc == "outflow" else C["RSL_BC_EQ"]
+    p.tau_mode = {"const": C["RSL_TAU_CONST"], "etas": C["RSL_TAU_ETAS"], "inf": C["RSL_TAU_INF"]}[tau_mode]
+    p.gas = C["RSL_GAS_IDEAL"] if gas == "ideal" else C["RSL_GAS_PARTON"]
+    p.flags = C["RSL_FLAG_FORCE_UNSTABLE"] if force else 0
+    p.z_lo, p.z_hi = z_lo, z_hi
+    p.n_L, p.T_L, p.n_R, p.T_R = nL, TL, nR, TR
+    p.tau_r, p.tau_aw0, p.lambda_ref, p.kappa = tau_r, tau_aw0, lambda_ref, kappa
+    return p
+
+
+class Instance:
+    """One problem instance: caller-side buffers (torch uint8 tensors on the GPU)
+    for the state f and the work area, plus the host-side time."""
+
+    def __init__(self, quad, problem, device="cuda"):
+        self.quad, self.p = quad, problem
+        fb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        check(_lib.rsl_sizes(quad.handle, ctypes.byref(problem), ctypes.byref(fb), ctypes.byref(wb)))
+        self.f_buf = torch.empty(fb.value, dtype=torch.uint8, device=device)
+        self.work = torch.empty(wb.value, dtype=torch.uint8, device=device)
+        self.t = 0.0
+        self.nz = problem.nz
+        self.pitch = _lib.rsl_pitch(problem.nz) if problem.problem == C["RSL_SOD"] else 1
+        self.tdtype = torch.float64 if problem.dtype == C["RSL_F64"] else torch.float32
+
+    def _ptrs(self):
+        return ctypes.c_void_p(self.f_buf.data_ptr()), ctypes.c_void_p(self.work.data_ptr())
+
+    def init(self, t0=0.0, stream=None):
+        f, w = self._ptrs()
+        check(_lib.rsl_init(self.quad.handle, ctypes.byref(self.p), f, w, _stream(stream)))
+        self.t = float(t0)
+
+    def step(self, dt, nsteps=1, stream=None):
+        f, w = self._ptrs()
+        t = ctypes.c_double(self.t)
+        check(_lib.rsl_step(self.quad.handle, ctypes.byref(self.p), f, w, ctypes.byref(t), float(dt),
+                            int(nsteps), _stream(stream)))
+        self.t = t.value
+
+    def f(self):
+        """[V, nz] view of the state (no copy)."""
+        es = 8 if self.tdtype == torch.float64 else 4
+        n = self.f_buf.numel() // es
+        flat = self.f_buf.view(self.tdtype)[:n]
+        return flat[: self.quad.V * self.pitch].view(self.quad.V, self.pitch)[:, : self.nz]
+
+    def set_f(self, values):
+        self.f().copy_(torch.as_tensor(values, dtype=self.tdtype))
+
+    def moments(self, stream=None):
+        out = torch.empty((self.nz, C["RSL_NMOM"]), dtype=torch.float64, device=self.f_buf.device)
+        f, w = self._ptrs()
+        check(_lib.rsl_moments(self.quad.handle, ctypes.byref(self.p), f, w, ctypes.c_void_p(out.data_ptr()),
+                               _stream(stream)))
+        return out
+
+    def status(self, stream=None):
+        _, w = self._ptrs()
+        return _lib.rsl_status(self.quad.handle, ctypes.byref(self.p), w, _stream(stream))
+
+
+_sig("rsl_batch_create", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(Problem), _dp, ctypes.c_int,
+                                        ctypes.POINTER(_vp)])
+_sig("rsl_batch_free", None, [_vp])
+_sig("rsl_batch_sizes", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)])
+_sig("rsl_batch_offset", ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)])
+_sig("rsl_batch_time", ctypes.c_int, [_vp, ctypes.c_int, _dp])
+_sig("rsl_batch_init", ctypes.c_int, [_vp, _vp, _vp, _vp])
+_sig("rsl_batch_step", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
+_sig("rsl_batch_stage", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
+_sig("rsl_batch_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
+_sig("rsl_batch_status", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)])
+
+
+class Batch:
+    """Many instances (one kind, one dtype) advanced together; see rsl_batch_* in rsl.h."""
+
+    def __init__(self, quads, problems, dts, device="cuda"):
+        n = len(problems)
+        self.quads = list(quads)            # keep the handles alive
+        self.problems = (Problem * n)(*problems)
+        qarr = (_vp * n)(*[q.handle for q in self.quads])
+        dtarr = (ctypes.c_double * n)(*[float(x) for x in dts])
+        h = _vp()
+        check(_lib.rsl_batch_create(qarr, self.problems, dtarr, n, ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        fb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        check(_lib.rsl_batch_sizes(h, ctypes.byref(fb), ctypes.byref(wb)))
+        self.f_buf = torch.empty(fb.value, dtype=torch.uint8, device=device)
+        self.work = torch.empty(wb.value, dtype=torch.uint8, device=device)
+        self.tdtype = torch.float64 if problems[0].dtype == C["RSL_F64"] else torch.float32
+
+    def _ptrs(self):
+        return ctypes.c_void_p(self.f_buf.data_ptr()), ctypes.c_void_p(self.work.data_ptr())
+
+    def init(self, stream=None):
+        f, w = self._ptrs()
+        check(_lib.rsl_batch_init(self._h, f, w, _stream(stream)))
+
+    def step(self, nsteps=1, stream=None):
+        f, w = self._ptrs()
+        check(_lib.rsl_batch_step(self._h, f, w, int(nsteps), _stream(stream)))
+
+    def stage(self, s, stream=None):
+        f, w = self._ptrs()
+        check(_lib.rsl_batch_stage(self._h, f, w, int(s), _stream(stream)))
+
+    def time(self, i):
+        t = ctypes.c_double(0)
+        check(_lib.rsl_batch_time(self._h, i, ctypes.byref(t)))
+        return t.value
+
+    def f(self, i):
+        """[V, nz] view of instance i's state (no copy)."""
+        off = ctypes.c_size_t(0)
+        check(_lib.rsl_batch_offset(self._h, i, ctypes.byref(off)))
+        p, q = self.problems[i], self.quads[i]
+        es = 8 if self.tdtype == torch.float64 else 4
+        nz = p.nz
+        pitch = _lib.rsl_pitch(nz) if p.problem == C["RSL_SOD"] else 1
+        flat = self.f_buf[off.value: off.value + q.V * pitch * es].view(self.tdtype)
+        return flat.view(q.V, pitch)[:, :nz]
+
+    def moments(self, stream=None):
+        rows = sum(p.nz if p.problem == C["RSL_SOD"] else 1 for p in self.problems)
+        out = torch.empty((rows, C["RSL_NMOM"]), dtype=torch.float64, device=self.f_buf.device)
+        f, w = self._ptrs()
+        check(_lib.rsl_batch_moments(self._h, f, w, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def status(self, stream=None):
+        _, w = self._ptrs()
+        bad = ctypes.c_int(-1)
+        rc = _lib.rsl_batch_status(self._h, w, _stream(stream), ctypes.byref(bad))
+        return rc, bad.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.rsl_batch_free(h)
+            self._h = None

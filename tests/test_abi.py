@@ -1,0 +1,82 @@
+"""Host-side checks of librsl: it loads, exports every entry point that
+include/rsl.h declares, validates arguments without touching a GPU, and builds
+velocity-set tables that agree with the oracle's independently computed ones
+(no GPU compute is called here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1612_01287_amd", "librsl.so")
+
+
+@pytest.fixture(scope="module")
+def rsl():
+    if not os.path.exists(LIB):
+        from paper_1612_01287_amd import build
+        build.build()
+    from paper_1612_01287_amd import rsl as mod
+    return mod
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "rsl.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsl_\w+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(rsl):
+    names = header_functions()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_argument_validation(rsl):
+    h = ctypes.c_void_p()
+    f = rsl.lib().rsl_make_quadrature
+    HO = rsl.RSL_QUAD_HOST_ONLY
+    assert f(3, 8, 2, 3, 1.0, HO, ctypes.byref(h)) == rsl.RSL_EUNSUPPORTED       # N_L != 1
+    assert f(3, 8, 1, 7, 1.0, HO, ctypes.byref(h)) == rsl.RSL_EUNSUPPORTED       # N_Omega > 6
+    assert f(3, 3, 1, 3, 1.0, HO, ctypes.byref(h)) == rsl.RSL_EINVAL             # Q_xi <= N_Omega
+    assert f(1, 8, 1, 3, 1.0, HO, ctypes.byref(h)) == rsl.RSL_EINVAL             # Q_L < 2
+    assert f(3, 8, 1, 3, -1.0, HO, ctypes.byref(h)) == rsl.RSL_EINVAL            # T0 <= 0
+    assert not h.value
+    assert b"T0" in rsl.lib().rsl_last_error()
+    q = rsl.Quadrature(3, 8, 3, host_only=True)
+    # a host-only handle cannot drive kernels: rejected before any device call
+    p = rsl.make_problem(nz=400)
+    t = ctypes.c_double(0.0)
+    rc = rsl.lib().rsl_step(q.handle, ctypes.byref(p), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                            ctypes.byref(t), 1e-3, 1, None)
+    assert rc == rsl.RSL_EINVAL
+    fb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert rsl.lib().rsl_sizes(q.handle, ctypes.byref(p), ctypes.byref(fb), ctypes.byref(wb)) == 0
+    assert fb.value == 24 * rsl.lib().rsl_pitch(400) * 8
+    assert wb.value >= 2 * fb.value
+    bad = rsl.make_problem(nz=3)
+    assert rsl.lib().rsl_sizes(q.handle, ctypes.byref(bad), ctypes.byref(fb), ctypes.byref(wb)) == rsl.RSL_EINVAL
+    bad = rsl.make_problem(nz=100, nR=-1.0)
+    assert rsl.lib().rsl_sizes(q.handle, ctypes.byref(bad), ctypes.byref(fb), ctypes.byref(wb)) == rsl.RSL_EINVAL
+    bad = rsl.make_problem(kind="bjorken", gas="parton")
+    assert rsl.lib().rsl_sizes(q.handle, ctypes.byref(bad), ctypes.byref(fb), ctypes.byref(wb)) == 0
+    assert rsl.lib().rsl_pitch(1) == 64 and rsl.lib().rsl_pitch(64) == 64 and rsl.lib().rsl_pitch(65) == 128
+
+
+@pytest.mark.parametrize("QL,Q", [(2, 6), (3, 8), (3, 17), (2, 100), (3, 200)])
+def test_tables_match_oracle(rsl, QL, Q):
+    import oracle
+    vs = oracle.VelocitySet(QL, Q, min(Q - 1, 4))
+    q = rsl.Quadrature(QL, Q, min(Q - 1, 4), host_only=True)
+    assert np.max(np.abs(q.table(rsl.RSL_TAB_XI) - vs.xi)) < 4e-16
+    assert np.max(np.abs(q.table(rsl.RSL_TAB_WXI) - vs.wxi) / vs.wxi) < 4e-15
+    assert np.max(np.abs(q.table(rsl.RSL_TAB_PBAR) - vs.pb) / vs.pb) < 4e-16
+    assert np.max(np.abs(q.table(rsl.RSL_TAB_WL) - vs.wL) / vs.wL) < 4e-15
+    KL = q.table(rsl.RSL_TAB_KL).reshape(QL, QL)
+    assert np.max(np.abs(KL - vs.KL)) < 1e-14 * np.max(np.abs(vs.KL))
+    KP = q.table(rsl.RSL_TAB_KP).reshape(Q, Q)
+    assert np.max(np.abs(KP - vs.KP)) < 1e-13 * np.max(np.abs(vs.KP))
