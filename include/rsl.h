@@ -184,6 +184,12 @@ int rsl_batch_time(const rsl_batch* b, int i, double* t);
 int rsl_batch_init(rsl_batch* b, void* f_dev, void* work_dev, void* hip_stream);
 /* nsteps RK3 steps of every instance (eq. rk3 with L_Sod or L_Bjorken). */
 int rsl_batch_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream);
+/* The same nsteps steps replayed from a HIP graph: captured on the first call
+ * (and again whenever f_dev, work_dev, nsteps or the stream change), then
+ * launched with one hipGraphLaunch per call.  Needs an explicit stream; the
+ * graph holds kernel launches and event waits only.  Results are bitwise
+ * those of rsl_batch_step. */
+int rsl_batch_graph_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream);
 /* One RK3 stage (1, 2 or 3) of every Sod instance, without advancing the
  * host-side times: stage s reads f_n and the stage field s-1 and writes stage
  * field s (stage 3 writes f_{n+1} over f_n).  For custom drivers and timing. */

@@ -137,22 +137,31 @@ int rsl_make_quadrature(int Q_L, int Q_xi, int N_L, int N_Omega, double T0, int 
     if (rc != RSL_OK) { delete q; return rc; }
     if (!(flags & RSL_QUAD_HOST_ONLY)) {
         const int V = q->V, Q = q->Q, QL = q->QL;
-        std::vector<double> wxw(V), pk(QL), L1(QL);
+        std::vector<double> wxw(V), pk(QL), L1(QL), xv(V), pv(V), l1v(V), Pv((size_t)(q->NOm + 1) * V);
         for (int k = 0; k < QL; ++k) {
             pk[k] = T0 * q->pbar[k];
             L1[k] = 3.0 - q->pbar[k];
-            for (int j = 0; j < Q; ++j) wxw[k * Q + j] = q->wxi[j] * q->wL[k];
+            for (int j = 0; j < Q; ++j) {
+                const int v = k * Q + j;
+                wxw[v] = q->wxi[j] * q->wL[k];
+                xv[v] = q->xi[j];
+                pv[v] = pk[k];
+                l1v[v] = L1[k];
+                for (int m = 0; m <= q->NOm; ++m) Pv[(size_t)m * V + v] = q->Pm[(size_t)m * Q + j];
+            }
         }
-        const std::vector<double>* parts[] = {&q->xi, &wxw, &pk, &L1, &q->Pm, &q->ser, &q->thr, &q->KL, &q->KP};
-        size_t off[9], total = 0;
-        for (int i = 0; i < 9; ++i) {
+        const std::vector<double>* parts[] = {&q->xi, &wxw, &pk, &L1, &q->Pm, &q->ser, &q->thr, &q->KL, &q->KP,
+                                              &xv, &pv, &l1v, &Pv};
+        constexpr int NP = 13;
+        size_t off[NP], total = 0;
+        for (int i = 0; i < NP; ++i) {
             off[i] = total;
             total += align_up(parts[i]->size() * sizeof(double), 256);
         }
         if ((rc = hip_check(hipGetDevice(&q->device), "hipGetDevice")) != RSL_OK) { delete q; return rc; }
         if ((rc = hip_check(hipMalloc(&q->dmem, total), "hipMalloc(tables)")) != RSL_OK) { delete q; return rc; }
         std::vector<char> host(total, 0);
-        for (int i = 0; i < 9; ++i) std::memcpy(host.data() + off[i], parts[i]->data(), parts[i]->size() * sizeof(double));
+        for (int i = 0; i < NP; ++i) std::memcpy(host.data() + off[i], parts[i]->data(), parts[i]->size() * sizeof(double));
         rc = hip_check(hipMemcpy(q->dmem, host.data(), total, hipMemcpyHostToDevice), "hipMemcpy(tables)");
         if (rc != RSL_OK) { (void)hipFree(q->dmem); delete q; return rc; }
         char* b = (char*)q->dmem;
@@ -165,6 +174,10 @@ int rsl_make_quadrature(int Q_L, int Q_xi, int N_L, int N_Omega, double T0, int 
         q->dev.thr = (const double*)(b + off[6]);
         q->dev.KL = (const double*)(b + off[7]);
         q->dev.KP = (const double*)(b + off[8]);
+        q->dev.xv = (const double*)(b + off[9]);
+        q->dev.pv = (const double*)(b + off[10]);
+        q->dev.l1v = (const double*)(b + off[11]);
+        q->dev.Pv = (const double*)(b + off[12]);
         q->on_device = true;
     }
     *out = q;

@@ -26,7 +26,17 @@ struct rsl_batch {
     rsl::BatchLaunch launch{};
     size_t bj_lds = 0;
     int device = -1;
-    int stash_limit = -1;                   // -1: chosen by the library
+    // concurrency across velocity classes: helper streams joined by events
+    bool streams_ready = false;
+    hipStream_t aux[rsl::kClasses] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[rsl::kClasses] = {};
+    // captured graph of nsteps steps
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    void* g_f = nullptr;
+    void* g_w = nullptr;
+    int g_steps = -1;
+    hipStream_t g_stream = nullptr;
 };
 
 namespace rsl {
@@ -38,17 +48,19 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // the per-cell work (Landau frame, equilibrium coefficients) is ~25 updates.
 double tile_cost(const rsl_quad* q) { return (double)kLanes * (q->V + 25.0); }
 
-std::vector<int2> schedule(const rsl_batch* b) {
+std::vector<int2> schedule(const rsl_batch* b, int cls) {
     const int X = 8;
-    std::vector<int> order(b->n);
-    std::iota(order.begin(), order.end(), 0);
+    std::vector<int> order;
+    for (int i = 0; i < b->n; ++i)
+        if (stage_class_of(b->quads[i]->V) == cls) order.push_back(i);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int c) { return b->quads[a]->V > b->quads[c]->V; });
     std::vector<std::vector<std::pair<double, int2>>> q(X);
     std::vector<double> load(X, 0.0);
     for (int i : order) {
-        const int nt = (b->probs[i].nz + kTileCells - 1) / kTileCells;
-        const double c = tile_cost(b->quads[i]);
+        const int tc = stage_tile_cells(cls);
+        const int nt = (b->probs[i].nz + tc - 1) / tc;
+        const double c = tile_cost(b->quads[i]) * tc / kTileCells;
         const int run = std::max(1, (nt + X - 1) / X);
         for (int t0 = 0; t0 < nt; t0 += run) {
             const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -73,40 +85,83 @@ std::vector<int2> schedule(const rsl_batch* b) {
 }  // namespace
 
 int batch_upload(rsl_batch* b) {
-    std::vector<int2> items;
-    if (b->kind == RSL_SOD) {
-        items = schedule(b);
-        const size_t es = b->dtype == RSL_F64 ? 8 : 4;
-        // LDS windows: by default every instance whose window fits in 64 KiB
-        // (two workgroups per CU) uses one, unless all fit in the per-WG limit.
-        size_t maxw = 0, limit = b->stash_limit >= 0 ? (size_t)b->stash_limit : 0;
-        for (int i = 0; i < b->n; ++i) maxw = std::max(maxw, (size_t)b->quads[i]->V * kWin * es);
-        if (b->stash_limit < 0) {
-            const size_t cap = sod_max_lds() - sod_red_bytes();
-            limit = maxw <= cap ? maxw : 64 * 1024 - sod_red_bytes();
+    std::vector<std::vector<int2>> items(kClasses);
+    size_t total = 0;
+    if (b->kind == RSL_SOD)
+        for (int c = 0; c < kClasses; ++c) {
+            items[c] = schedule(b, c);
+            total += align_up(sizeof(int2) * items[c].size(), 256);
         }
-        size_t used = 0;
-        for (int i = 0; i < b->n; ++i) {
-            const size_t w = (size_t)b->quads[i]->V * kWin * es;
-            if (w <= limit) used = std::max(used, w);
-        }
-        b->launch.stash_limit = (int)limit;
-        b->launch.lds_bytes = sod_red_bytes() + used;
-    }
     const size_t dbytes = align_up(sizeof(InstDesc) * b->n, 256);
-    const size_t ibytes = sizeof(int2) * items.size();
-    int rc = hip_check(hipMalloc(&b->dmem, dbytes + std::max<size_t>(ibytes, 256)), "hipMalloc(batch)");
+    int rc = hip_check(hipMalloc(&b->dmem, dbytes + std::max<size_t>(total, 256)), "hipMalloc(batch)");
     if (rc) return rc;
     rc = hip_check(hipMemcpy(b->dmem, b->host_desc.data(), sizeof(InstDesc) * b->n, hipMemcpyHostToDevice),
                    "hipMemcpy(batch descriptors)");
-    if (rc) return rc;
-    if (ibytes)
-        rc = hip_check(hipMemcpy((char*)b->dmem + dbytes, items.data(), ibytes, hipMemcpyHostToDevice),
-                       "hipMemcpy(batch items)");
-    b->launch.descs = (const InstDesc*)b->dmem;
-    b->launch.items = (const int2*)((char*)b->dmem + dbytes);
-    b->launch.nitems = (int)items.size();
+    size_t off = dbytes;
+    for (int c = 0; c < kClasses && rc == RSL_OK; ++c) {
+        StageClass& cl = b->launch.cl[c];
+        cl.cls = c;
+        cl.descs = (const InstDesc*)b->dmem;
+        cl.items = (const int2*)((char*)b->dmem + off);
+        cl.nitems = (int)items[c].size();
+        if (cl.nitems)
+            rc = hip_check(hipMemcpy((char*)b->dmem + off, items[c].data(), sizeof(int2) * items[c].size(),
+                                     hipMemcpyHostToDevice), "hipMemcpy(batch items)");
+        off += align_up(sizeof(int2) * items[c].size(), 256);
+    }
     return rc;
+}
+
+int batch_streams(rsl_batch* b) {
+    if (b->streams_ready) return RSL_OK;
+    int rc = hip_check(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "hipEventCreate");
+    for (int c = 0; c < kClasses && rc == RSL_OK; ++c) {
+        rc = hip_check(hipStreamCreateWithFlags(&b->aux[c], hipStreamNonBlocking), "hipStreamCreate");
+        if (rc == RSL_OK) rc = hip_check(hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming), "hipEventCreate");
+    }
+    b->streams_ready = rc == RSL_OK;
+    return rc;
+}
+
+// One RK stage of every Sod instance: the velocity classes run as concurrent
+// launches (forked from and joined back into the caller's stream), so that
+// small classes do not leave the GPU idle behind each other.
+int batch_stage_all(rsl_batch* b, int stage, char* f, char* w, hipStream_t s) {
+    int used[kClasses], nu = 0;
+    for (int c = 0; c < kClasses; ++c)
+        if (b->launch.cl[c].nitems) used[nu++] = c;
+    if (nu <= 1) return nu ? launch_sod_class_stage(b->launch.cl[used[0]], b->dtype, stage, f, w, s) : RSL_OK;
+    int rc = batch_streams(b);
+    if (rc) return rc;
+    if ((rc = hip_check(hipEventRecord(b->ev_fork, s), "hipEventRecord"))) return rc;
+    for (int k = 1; k < nu && rc == RSL_OK; ++k)
+        rc = hip_check(hipStreamWaitEvent(b->aux[k], b->ev_fork, 0), "hipStreamWaitEvent");
+    for (int k = 0; k < nu && rc == RSL_OK; ++k)
+        rc = launch_sod_class_stage(b->launch.cl[used[k]], b->dtype, stage, f, w, k ? b->aux[k] : s);
+    for (int k = 1; k < nu && rc == RSL_OK; ++k) {
+        rc = hip_check(hipEventRecord(b->ev_join[k], b->aux[k]), "hipEventRecord");
+        if (rc == RSL_OK) rc = hip_check(hipStreamWaitEvent(s, b->ev_join[k], 0), "hipStreamWaitEvent");
+    }
+    return rc;
+}
+
+int batch_steps(rsl_batch* b, char* f, char* w, int nsteps, hipStream_t s) {
+    int rc = RSL_OK;
+    if (b->kind == RSL_SOD) {
+        for (int it = 0; it < nsteps && rc == RSL_OK; ++it)
+            for (int st = 1; st <= 3 && rc == RSL_OK; ++st) rc = batch_stage_all(b, st, f, w, s);
+    } else if (nsteps > 0) {
+        rc = launch_bj_batch_steps((const InstDesc*)b->dmem, b->n, b->bj_lds, b->dtype, f, w, 0.0, 0.0, nsteps, s);
+    }
+    return rc;
+}
+
+void batch_drop_graph(rsl_batch* b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->g_steps = -1;
 }
 
 }  // namespace rsl
@@ -170,6 +225,14 @@ int rsl_batch_create(const rsl_quad* const* quads, const rsl_problem* problems, 
 
 void rsl_batch_free(rsl_batch* b) {
     if (!b) return;
+    batch_drop_graph(b);
+    if (b->streams_ready) {
+        (void)hipEventDestroy(b->ev_fork);
+        for (int c = 0; c < kClasses; ++c) {
+            (void)hipStreamDestroy(b->aux[c]);
+            (void)hipEventDestroy(b->ev_join[c]);
+        }
+    }
     if (b->dmem) (void)hipFree(b->dmem);
     delete b;
 }
@@ -208,25 +271,50 @@ int rsl_batch_stage(rsl_batch* b, void* f_dev, void* work_dev, int stage, void* 
     if (!b || !f_dev || !work_dev) return set_error(RSL_EINVAL, "null argument");
     if (b->kind != RSL_SOD) return set_error(RSL_EINVAL, "single stages exist for Sod batches only");
     if (stage < 1 || stage > 3) return set_error(RSL_EINVAL, "stage must be 1, 2 or 3");
-    return launch_sod_batch_stage(b->launch, b->dtype, stage, (char*)f_dev, (char*)work_dev, (hipStream_t)hip_stream);
+    return batch_stage_all(b, stage, (char*)f_dev, (char*)work_dev, (hipStream_t)hip_stream);
 }
 
 int rsl_batch_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream) {
     if (!b || !f_dev || !work_dev) return set_error(RSL_EINVAL, "null argument");
     if (nsteps < 0) return set_error(RSL_EINVAL, "nsteps < 0");
-    hipStream_t s = (hipStream_t)hip_stream;
-    int rc = RSL_OK;
-    if (b->kind == RSL_SOD) {
-        for (int it = 0; it < nsteps && rc == RSL_OK; ++it)
-            for (int st = 1; st <= 3 && rc == RSL_OK; ++st)
-                rc = launch_sod_batch_stage(b->launch, b->dtype, st, (char*)f_dev, (char*)work_dev, s);
-    } else if (nsteps > 0) {
-        rc = launch_bj_batch_steps(b->launch.descs, b->n, b->bj_lds, b->dtype, (char*)f_dev, (char*)work_dev, 0.0,
-                                   0.0, nsteps, s);
-    }
+    const int rc = batch_steps(b, (char*)f_dev, (char*)work_dev, nsteps, (hipStream_t)hip_stream);
     if (rc == RSL_OK)
         for (int i = 0; i < b->n; ++i) b->t[i] += nsteps * b->dt[i];
     return rc;
+}
+
+int rsl_batch_graph_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream) {
+    if (!b || !f_dev || !work_dev) return set_error(RSL_EINVAL, "null argument");
+    if (nsteps <= 0) return set_error(RSL_EINVAL, "nsteps must be > 0");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (!s) return set_error(RSL_EINVAL, "graph replay needs an explicit (non-default) stream");
+    int rc = RSL_OK;
+    if (!b->gexec || b->g_f != f_dev || b->g_w != work_dev || b->g_steps != nsteps || b->g_stream != s) {
+        batch_drop_graph(b);
+        if (b->kind == RSL_SOD && (rc = batch_streams(b))) return rc;
+        if ((rc = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")))
+            return rc;
+        rc = batch_steps(b, (char*)f_dev, (char*)work_dev, nsteps, s);
+        hipGraph_t g = nullptr;
+        const int rc2 = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
+        if (rc == RSL_OK) rc = rc2;
+        if (rc != RSL_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        b->graph = g;
+        if ((rc = hip_check(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0), "hipGraphInstantiate"))) {
+            batch_drop_graph(b);
+            return rc;
+        }
+        b->g_f = f_dev;
+        b->g_w = work_dev;
+        b->g_steps = nsteps;
+        b->g_stream = s;
+    }
+    if ((rc = hip_check(hipGraphLaunch(b->gexec, s), "hipGraphLaunch"))) return rc;
+    for (int i = 0; i < b->n; ++i) b->t[i] += nsteps * b->dt[i];
+    return RSL_OK;
 }
 
 int rsl_batch_moments(rsl_batch* b, const void* f_dev, void* work_dev, double* out_dev, void* hip_stream) {

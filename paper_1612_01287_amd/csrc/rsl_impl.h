@@ -34,6 +34,11 @@ struct QuadDev {
     const double* thr;   // [kSeriesTerms]  beta^2 below which i terms suffice
     const double* KL;    // [QL*QL]
     const double* KP;    // [Q*Q]
+    // per-velocity copies, v = k*Q + j, read with uniform (scalar) loads
+    const double* xv;    // [V]      xi_j
+    const double* pv;    // [V]      p_k
+    const double* l1v;   // [V]      L_1(pbar_k)
+    const double* Pv;    // [(NOm+1)*V]  P_m(xi_j), row m
 };
 
 // Everything a kernel needs about one problem instance.  Passed by value as a
@@ -66,13 +71,17 @@ __host__ __device__ inline void rebase(InstDesc& d, char* fbase, char* wbase) {
     d.clock = (double*)(wbase + (size_t)d.clock);
 }
 
-// One batched launch: device descriptor table and work-item list.
-struct BatchLaunch {
+// Work items of one velocity-set class (see stage_class_of) in a batch.
+struct StageClass {
+    int cls;                 // kernel variant
     const InstDesc* descs;   // device [n]
     const int2* items;       // device [nitems], (instance, tile) or (-1, -1)
     int nitems;
-    int stash_limit;         // bytes of LDS window allowed per workgroup
-    size_t lds_bytes;        // dynamic LDS of the launch
+};
+
+constexpr int kClasses = 6;
+struct BatchLaunch {
+    StageClass cl[kClasses];
 };
 
 }  // namespace rsl
@@ -106,9 +115,9 @@ int launch_boundary_states(const InstDesc& d, double nL, double TL, double nR, d
 int launch_sod_init(const InstDesc& d, hipStream_t s);
 int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s);
 int launch_sod_moments(const InstDesc& d, const void* f, double* out, hipStream_t s);
-int launch_sod_batch_stage(const BatchLaunch& b, int dtype, int stage, char* fbase, char* wbase, hipStream_t s);
-size_t sod_red_bytes();
-size_t sod_max_lds();
+int launch_sod_class_stage(const StageClass& cl, int dtype, int stage, char* fbase, char* wbase, hipStream_t s);
+int stage_class_of(int V);
+int stage_tile_cells(int cls);
 int launch_bj_batch_steps(const InstDesc* descs, int n, size_t lds, int dtype, char* fbase, char* wbase,
                           double tau0, double dtau, int nsteps, hipStream_t s);
 int launch_bj_init(const InstDesc& d, double n0, double T0s, double tau0, hipStream_t s);

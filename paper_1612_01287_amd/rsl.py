@@ -206,6 +206,7 @@ _sig("rsl_batch_time", ctypes.c_int, [_vp, ctypes.c_int, _dp])
 _sig("rsl_batch_init", ctypes.c_int, [_vp, _vp, _vp, _vp])
 _sig("rsl_batch_step", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_stage", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
+_sig("rsl_batch_graph_step", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("rsl_batch_status", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)])
 
@@ -239,6 +240,11 @@ class Batch:
     def step(self, nsteps=1, stream=None):
         f, w = self._ptrs()
         check(_lib.rsl_batch_step(self._h, f, w, int(nsteps), _stream(stream)))
+
+    def graph_step(self, nsteps=1, stream=None):
+        """nsteps steps replayed from a captured HIP graph (needs a non-default stream)."""
+        f, w = self._ptrs()
+        check(_lib.rsl_batch_graph_step(self._h, f, w, int(nsteps), _stream(stream)))
 
     def stage(self, s, stream=None):
         f, w = self._ptrs()

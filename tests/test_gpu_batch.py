@@ -104,3 +104,24 @@ def test_bjorken_batch_equals_single(rsl):
     inst.step(1e-3, 200)
     inst.step(1e-3, 100)
     assert torch.equal(B.f(0), inst.f())
+
+
+def test_graph_replay_equals_eager(rsl):
+    """Steps replayed from the captured HIP graph equal eager steps bitwise, on
+    every replay, with eager work and synchronisations between replays."""
+    quads, probs, dts = _sod_ensemble(rsl, "f64", seed=21, n=7)
+    A = rsl.Batch(quads, probs, dts)
+    B = rsl.Batch(quads, probs, dts)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        A.init()
+        B.init()
+        for rep in range(4):
+            A.step(3)
+            B.graph_step(3)
+            junk = torch.randn(1000, device="cuda").sum()     # unrelated eager work
+            torch.cuda.synchronize()
+            for i in range(len(probs)):
+                assert torch.equal(A.f(i), B.f(i)), (rep, i)
+            assert float(junk) == float(junk)
+        assert B.time(0) == pytest.approx(12 * dts[0], rel=1e-14)
