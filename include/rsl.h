@@ -197,9 +197,57 @@ int rsl_batch_stage(rsl_batch* b, void* f_dev, void* work_dev, int stage, void* 
 /* Per-cell fields of every instance, rows concatenated in instance order
  * (nz rows per Sod instance, one per Bjorken instance), RSL_NMOM per row. */
 int rsl_batch_moments(rsl_batch* b, const void* f_dev, void* work_dev, double* out_dev, void* hip_stream);
+/* Kernel path of a Bjorken batch: -1 automatic (matrix cores when every
+ * instance fits: Q_L <= 4 and a padded Q_xi x 16 Q_L stage field within the
+ * LDS), 0 one workgroup per instance on the vector units, 1 matrix cores
+ * (RSL_EUNSUPPORTED if not available).  The two paths agree to rounding. */
+int rsl_batch_set_path(rsl_batch* b, int path);
 /* Synchronises and reads every instance's status word; *first_bad (if not
  * NULL) receives the first failing instance or -1. */
 int rsl_batch_status(rsl_batch* b, void* work_dev, void* hip_stream, int* first_bad);
+
+/* ------------------------------------------------ learned T^{mu nu} correction
+ * Not part of the paper: a per-cell network that maps the local moments of a
+ * low-order velocity set to the difference between a high-order and the
+ * low-order T^{00}, T^{0z}, T^{zz}.  Features of cell s: M_{a,r} =
+ * sum_jk f_jk p_k^a xi_j^r (a in {0,1}, r in 0..7; eq. macro_jk extended to
+ * r <= 7) of cells s-2..s+2 (end cells repeated), the a = 0 ones divided by the
+ * centre's N^0, the a = 1 ones by its T^00, then log tau_r: 81 floats.
+ * Network: 81 -> 128 -> 128 -> 3, ReLU, parameters W1 [81][128], b1, W2
+ * [128][128], b2, W3 [128][3], b3 (27395 values) in an fp32 master copy and a
+ * bf16 compute copy; matrix products in bf16 with fp32 accumulation.
+ * Output y = (T_hi - T_lo) / T^00_lo for (T^00, T^0z, T^zz). */
+#define RSL_MLP_IN      81
+#define RSL_MLP_HIDDEN  128
+#define RSL_MLP_OUT     3
+#define RSL_MLP_NPARAM  27395
+
+/* feat_dev[nz][81] (fp32) from one Sod instance's f. */
+int rsl_mlp_features(const rsl_quad* q, const rsl_problem* p, const void* f_dev, double log_tau, float* feat_dev,
+                     void* hip_stream);
+/* bf16 (round to nearest even) copy of fp32 parameters. */
+int rsl_mlp_to_bf16(const float* params, unsigned short* params_bf16, void* hip_stream);
+/* y[n][3] = net(x[n][81]).  h1, h2 ([n][128] bf16 each) receive the hidden
+ * activations for rsl_mlp_backward, or are both NULL. */
+int rsl_mlp_forward(const unsigned short* params_bf16, const float* x, int n, float* y, unsigned short* h1,
+                    unsigned short* h2, void* hip_stream);
+/* grad[27395] = d/dparams of mean((y - t)^2) over the n x 3 outputs, from the
+ * activations of the matching forward call (grad is overwritten). */
+int rsl_mlp_backward(const unsigned short* params_bf16, const float* x, const unsigned short* h1,
+                     const unsigned short* h2, const float* y, const float* t, int n, float* grad, void* hip_stream);
+/* One Adam step (step >= 1, bias-corrected) on the fp32 parameters; refreshes
+ * the bf16 copy. */
+int rsl_mlp_adam(float* params, const float* grad, float* m, float* v, unsigned short* params_bf16, int step, float lr,
+                 float beta1, float beta2, float eps, void* hip_stream);
+/* Moment rows m_lo, m_hi: RSL_NMOM doubles per cell (rsl_moments output).
+ * mode 0: t_out[n][3] = (T_hi - T_lo) / T^00_lo (training targets);
+ * mode 1: t_corr[n][3] = T_lo + y T^00_lo (corrected T^00, T^0z, T^zz). */
+int rsl_mlp_tmunu(const double* m_lo, const double* m_hi, const float* y, int n, int mode, float* t_out,
+                  double* t_corr, void* hip_stream);
+/* Sets *flag_dev (atomic OR 1) if any feature lies outside [lo[c], hi[c]]
+ * (the range seen in training): the caller then falls back to the high-order
+ * solve. */
+int rsl_mlp_guard(const float* x, int n, const float* lo, const float* hi, unsigned* flag_dev, void* hip_stream);
 
 #ifdef __cplusplus
 }

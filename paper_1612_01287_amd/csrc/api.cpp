@@ -150,9 +150,25 @@ int rsl_make_quadrature(int Q_L, int Q_xi, int N_L, int N_Omega, double T0, int 
                 for (int m = 0; m <= q->NOm; ++m) Pv[(size_t)m * V + v] = q->Pm[(size_t)m * Q + j];
             }
         }
+        const int Qp = (Q + 15) / 16 * 16, RT = Qp / 16, KT = Qp / 4;
+        std::vector<double> KPt((size_t)Qp * Qp, 0.0);
+        for (int rt = 0; rt < RT; ++rt)
+            for (int kk = 0; kk < KT; ++kk)
+                for (int l = 0; l < 64; ++l) {
+                    const int row = 16 * rt + l % 16, col = 4 * kk + l / 16;
+                    if (row < Q && col < Q) KPt[((size_t)rt * KT + kk) * 64 + l] = q->KP[(size_t)row * Q + col];
+                }
+        // velocity order by ascending xi_j (so by its sign), radial node inner; as
+        // doubles in the table block, converted to int below
+        std::vector<double> vpd(V);
+        {
+            int o = 0;
+            for (int j = 0; j < Q; ++j)
+                for (int k = 0; k < QL; ++k) vpd[o++] = (double)(k * Q + j);
+        }
         const std::vector<double>* parts[] = {&q->xi, &wxw, &pk, &L1, &q->Pm, &q->ser, &q->thr, &q->KL, &q->KP,
-                                              &xv, &pv, &l1v, &Pv};
-        constexpr int NP = 13;
+                                              &xv, &pv, &l1v, &Pv, &KPt, &vpd};
+        constexpr int NP = 15;
         size_t off[NP], total = 0;
         for (int i = 0; i < NP; ++i) {
             off[i] = total;
@@ -161,7 +177,9 @@ int rsl_make_quadrature(int Q_L, int Q_xi, int N_L, int N_Omega, double T0, int 
         if ((rc = hip_check(hipGetDevice(&q->device), "hipGetDevice")) != RSL_OK) { delete q; return rc; }
         if ((rc = hip_check(hipMalloc(&q->dmem, total), "hipMalloc(tables)")) != RSL_OK) { delete q; return rc; }
         std::vector<char> host(total, 0);
-        for (int i = 0; i < NP; ++i) std::memcpy(host.data() + off[i], parts[i]->data(), parts[i]->size() * sizeof(double));
+        for (int i = 0; i < NP - 1; ++i)
+            std::memcpy(host.data() + off[i], parts[i]->data(), parts[i]->size() * sizeof(double));
+        for (int v = 0; v < V; ++v) ((int*)(host.data() + off[NP - 1]))[v] = (int)vpd[v];
         rc = hip_check(hipMemcpy(q->dmem, host.data(), total, hipMemcpyHostToDevice), "hipMemcpy(tables)");
         if (rc != RSL_OK) { (void)hipFree(q->dmem); delete q; return rc; }
         char* b = (char*)q->dmem;
@@ -178,6 +196,8 @@ int rsl_make_quadrature(int Q_L, int Q_xi, int N_L, int N_Omega, double T0, int 
         q->dev.pv = (const double*)(b + off[10]);
         q->dev.l1v = (const double*)(b + off[11]);
         q->dev.Pv = (const double*)(b + off[12]);
+        q->dev.KPt = (const double*)(b + off[13]);
+        q->dev.vperm = (const int*)(b + off[14]);
         q->on_device = true;
     }
     *out = q;

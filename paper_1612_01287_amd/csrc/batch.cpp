@@ -37,6 +37,12 @@ struct rsl_batch {
     void* g_w = nullptr;
     int g_steps = -1;
     hipStream_t g_stream = nullptr;
+    // Bjorken: groups of up to 16 instances sharing one velocity set (matrix-core path)
+    int* groups = nullptr;        // device [ngroups][16]
+    int ngroups = 0;
+    size_t mfma_lds = 0;
+    bool use_mfma = false;
+    int bj_path = -1;             // -1 automatic, 0 per-instance kernel, 1 matrix cores
 };
 
 namespace rsl {
@@ -84,9 +90,40 @@ std::vector<int2> schedule(const rsl_batch* b, int cls) {
 
 }  // namespace
 
+// Bjorken groups: instances sharing one rsl_quad, 16 per group.
+std::vector<int> bj_groups(const rsl_batch* b) {
+    std::vector<int> order(b->n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return b->quads[a]->Q != b->quads[c]->Q ? b->quads[a]->Q > b->quads[c]->Q : b->quads[a] < b->quads[c];
+    });
+    std::vector<int> g;
+    for (size_t s = 0; s < order.size();) {
+        const rsl_quad* q = b->quads[order[s]];
+        std::vector<int> grp;
+        while (s < order.size() && b->quads[order[s]] == q && grp.size() < 16) grp.push_back(order[s++]);
+        grp.resize(16, -1);
+        g.insert(g.end(), grp.begin(), grp.end());
+    }
+    return g;
+}
+
 int batch_upload(rsl_batch* b) {
     std::vector<std::vector<int2>> items(kClasses);
     size_t total = 0;
+    std::vector<int> groups;
+    if (b->kind == RSL_BJORKEN) {
+        b->use_mfma = true;
+        for (int i = 0; i < b->n; ++i)
+            if (!bj_mfma_fits(b->quads[i]->Q, b->quads[i]->QL)) b->use_mfma = false;
+        if (b->use_mfma) {
+            groups = bj_groups(b);
+            b->ngroups = (int)groups.size() / 16;
+            for (int i = 0; i < b->n; ++i)
+                b->mfma_lds = std::max(b->mfma_lds, bj_mfma_lds_bytes(b->quads[i]->Q, b->quads[i]->QL));
+            total += align_up(sizeof(int) * groups.size(), 256);
+        }
+    }
     if (b->kind == RSL_SOD)
         for (int c = 0; c < kClasses; ++c) {
             items[c] = schedule(b, c);
@@ -108,6 +145,11 @@ int batch_upload(rsl_batch* b) {
             rc = hip_check(hipMemcpy((char*)b->dmem + off, items[c].data(), sizeof(int2) * items[c].size(),
                                      hipMemcpyHostToDevice), "hipMemcpy(batch items)");
         off += align_up(sizeof(int2) * items[c].size(), 256);
+    }
+    if (rc == RSL_OK && !groups.empty()) {
+        b->groups = (int*)((char*)b->dmem + off);
+        rc = hip_check(hipMemcpy(b->groups, groups.data(), sizeof(int) * groups.size(), hipMemcpyHostToDevice),
+                       "hipMemcpy(batch groups)");
     }
     return rc;
 }
@@ -151,7 +193,11 @@ int batch_steps(rsl_batch* b, char* f, char* w, int nsteps, hipStream_t s) {
         for (int it = 0; it < nsteps && rc == RSL_OK; ++it)
             for (int st = 1; st <= 3 && rc == RSL_OK; ++st) rc = batch_stage_all(b, st, f, w, s);
     } else if (nsteps > 0) {
-        rc = launch_bj_batch_steps((const InstDesc*)b->dmem, b->n, b->bj_lds, b->dtype, f, w, 0.0, 0.0, nsteps, s);
+        const bool mfma = b->use_mfma && b->bj_path != 0;
+        if (mfma)
+            rc = launch_bj_mfma((const InstDesc*)b->dmem, b->groups, b->ngroups, b->mfma_lds, b->dtype, f, w, nsteps, s);
+        else
+            rc = launch_bj_batch_steps((const InstDesc*)b->dmem, b->n, b->bj_lds, b->dtype, f, w, 0.0, 0.0, nsteps, s);
     }
     return rc;
 }
@@ -326,6 +372,14 @@ int rsl_batch_moments(rsl_batch* b, const void* f_dev, void* work_dev, double* o
         if (rc) return rc;
         row += b->probs[i].problem == RSL_SOD ? b->probs[i].nz : 1;
     }
+    return RSL_OK;
+}
+
+int rsl_batch_set_path(rsl_batch* b, int path) {
+    if (!b || path < -1 || path > 1) return set_error(RSL_EINVAL, "bad batch path");
+    if (path == 1 && !b->use_mfma) return set_error(RSL_EUNSUPPORTED, "matrix-core path not available for this batch");
+    b->bj_path = path;
+    batch_drop_graph(b);
     return RSL_OK;
 }
 

@@ -39,6 +39,10 @@ struct QuadDev {
     const double* pv;    // [V]      p_k
     const double* l1v;   // [V]      L_1(pbar_k)
     const double* Pv;    // [(NOm+1)*V]  P_m(xi_j), row m
+    const int* vperm;    // [V] velocities ordered by the sign of xi (negative, zero, positive):
+                         // the 32-lane stage kernels pair vperm[2p], vperm[2p+1]
+    const double* KPt;   // K^P zero-padded to Qp = 16 ceil(Q/16), in MFMA A-operand order:
+                         // [rt][kk][lane] = K^P[16 rt + lane % 16][4 kk + lane / 16]
 };
 
 // Everything a kernel needs about one problem instance.  Passed by value as a
@@ -122,6 +126,10 @@ int launch_bj_batch_steps(const InstDesc* descs, int n, size_t lds, int dtype, c
                           double tau0, double dtau, int nsteps, hipStream_t s);
 int launch_bj_init(const InstDesc& d, double n0, double T0s, double tau0, hipStream_t s);
 size_t bj_lds_bytes(int V);
+size_t bj_mfma_lds_bytes(int Q, int QL);
+bool bj_mfma_fits(int Q, int QL);
+int launch_bj_mfma(const InstDesc* descs, const int* groups, int ngroups, size_t lds, int dtype, char* fbase,
+                   char* wbase, int nsteps, hipStream_t s);
 int launch_bj_steps(const InstDesc& d, double tau0, double dtau, int nsteps, hipStream_t s);
 int launch_bj_moments(const InstDesc& d, const void* f, double* out, hipStream_t s);
 

@@ -138,9 +138,10 @@ __device__ __forceinline__ void feq_coef(double n, double T, double beta, double
 // w_q ~ delta_q / sigma_q^2 with delta = (1/10, 6/10, 3/10) and no epsilon
 // regulariser; the paper's limiting cases for vanishing indicators are
 // honoured: all equal -> ideal weights; two zero -> the two share by their
-// ideal weights; one zero -> that stencil alone.  The generic case is
-// evaluated with the common denominator sigma_1^2 sigma_2^2 sigma_3^2 so that
-// one division suffices.
+// ideal weights; one zero -> that stencil alone.  The common case uses the
+// common denominator sigma_1^2 sigma_2^2 sigma_3^2 (equal indicators then give
+// the ideal weights to rounding) and a reciprocal refined by two Newton steps;
+// exact zeros and products outside [1e-280, 1e280] take the explicit branch.
 __device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
     const double q1 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
     const double q2 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
@@ -154,18 +155,27 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
     const double u1 = s1 * s1, u2 = s2 * s2, u3 = s3 * s3;
     const double w1 = 0.1 * u2 * u3, w2 = 0.6 * u1 * u3, w3 = 0.3 * u1 * u2;
     const double den = w1 + w2 + w3;
-    if (s1 == s2 && s2 == s3) return 0.1 * q1 + 0.6 * q2 + 0.3 * q3;
-    if (den > 0.0 && den < INFINITY) return (w1 * q1 + w2 * q2 + w3 * q3) / den;
-    // limiting cases with exact zeros (or products out of range)
+    if (den > 1e-280 && den < 1e280) {
+        double r = __builtin_amdgcn_rcp(den);
+        double err = fma(-den, r, 1.0);
+        r = fma(r, err, r);
+        err = fma(-den, r, 1.0);
+        r = fma(r, err, r);
+        return (w1 * q1 + w2 * q2 + w3 * q3) * r;
+    }
+    if (s1 == s2 && s2 == s3) return 0.1 * q1 + 0.6 * q2 + 0.3 * q3;    // case (i), incl. all zero
     const int z1 = s1 == 0.0, z2 = s2 == 0.0, z3 = s3 == 0.0;
     const int nz = z1 + z2 + z3;
-    if (nz == 2) {
+    if (nz == 2) {                                                        // case (ii)
         const double dsum = 0.1 * z1 + 0.6 * z2 + 0.3 * z3;
         return (0.1 * z1 * q1 + 0.6 * z2 * q2 + 0.3 * z3 * q3) / dsum;
     }
-    if (nz == 1) return z1 ? q1 : (z2 ? q2 : q3);
-    // no zero but the product form over/underflowed: pairwise ratios
-    const double v1 = 0.1 / u1, v2 = 0.6 / u2, v3 = 0.3 / u3;
+    if (nz == 1) return z1 ? q1 : (z2 ? q2 : q3);                         // case (iii)
+    // no zero but the product form left the safe range: weights relative to the
+    // smallest indicator, delta_q (sigma_min / sigma_q)^2, all in [0, 1]
+    const double sm = fmin(s1, fmin(s2, s3));
+    const double g1 = sm / s1, g2 = sm / s2, g3 = sm / s3;
+    const double v1 = 0.1 * g1 * g1, v2 = 0.6 * g2 * g2, v3 = 0.3 * g3 * g3;
     return (v1 * q1 + v2 * q2 + v3 * q3) / (v1 + v2 + v3);
 }
 

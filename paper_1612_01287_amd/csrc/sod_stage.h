@@ -77,6 +77,32 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return (b & 7) * per + (b >> 3);
 }
 
+// Velocities of step i for wave w.  One slot (64 lanes per velocity): v = w + i W.
+// Two slots (32 lanes each): the pair vperm[2p], vperm[2p+1], p = w + i W, taken
+// from a list ordered by the sign of xi_j so that both slots usually move the
+// same way (the upwind branch then stays uniform).  All values are scalars.
+struct VelPair {
+    int va, vb;
+    bool ok_a, ok_b;
+};
+
+template <int S, int W>
+__device__ __forceinline__ VelPair vel_pair(const InstDesc& d, int w, int i) {
+    VelPair r;
+    if (S == 1) {
+        const int v = w + i * W;
+        r.ok_a = r.ok_b = v < d.V;
+        r.va = r.vb = min(v, d.V - 1);
+    } else {
+        const int ia = 2 * (w + i * W), ib = ia + 1;
+        r.ok_a = ia < d.V;
+        r.ok_b = ib < d.V;
+        r.va = ldc(d.tab.vperm, min(ia, d.V - 1));
+        r.vb = ldc(d.tab.vperm, min(ib, d.V - 1));
+    }
+    return r;
+}
+
 template <typename Tf, int STAGE, int W, int NV, int TW>
 __device__ __forceinline__ void stage_tile(const InstDesc& d, int tile, char* lds) {
     constexpr int G = kGroup;
@@ -85,7 +111,7 @@ __device__ __forceinline__ void stage_tile(const InstDesc& d, int tile, char* ld
     constexpr int WN = TW + 8;            // window entries per slot (TW + 5 used)
     const int lane = threadIdx.x & (kLanes - 1);
     // wave index as a scalar: the per-velocity tables then come through
-    // scalar loads and the upwind branch on xi_j is uniform when S = 1
+    // scalar loads and the upwind branch on xi_j is uniform
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     const int slot = S == 1 ? 0 : lane / TW;
     const int cl = lane & (TW - 1);
@@ -110,15 +136,13 @@ __device__ __forceinline__ void stage_tile(const InstDesc& d, int tile, char* ld
     const double* __restrict__ xv = d.tab.xv;
     const double* __restrict__ pv = d.tab.pv;
 
-    // velocity of this lane's slot at step i; va is the (scalar) slot-0 one
-    auto vel_of = [&](int i) { return w + slot * W + i * VS; };
-
     // ---- all stage-field loads of this wave in flight at once (clamped,
     //      branch-free addresses so the compiler keeps them outstanding)
     Tf ra[NV], rh[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-        const Tf* row = fcur + (size_t)min(vel_of(i), V - 1) * pitch;
+        const VelPair vp = vel_pair<S, W>(d, w, i);
+        const Tf* row = fcur + (size_t)(slot ? vp.vb : vp.va) * pitch;
         ra[i] = row[cc];
         rh[i] = cl < 5 ? row[hcc] : Tf(0);
     }
@@ -133,22 +157,20 @@ __device__ __forceinline__ void stage_tile(const InstDesc& d, int tile, char* ld
     // ordering point per group, and G independent WENO evaluations after it
 #pragma unroll
     for (int i0 = 0; i0 < NV; i0 += G) {
-        if (w + i0 * VS >= V) break;
+        if (!vel_pair<S, W>(d, w, i0).ok_a) break;
 #pragma unroll
         for (int i = i0; i < i0 + G && i < NV; ++i) {
-            const int va = w + i * VS;
-            if (va < V) {
-                const int v = vel_of(i);
-                const bool valid = v < V;
-                const int vb = min(va + W, V - 1);
+            const VelPair vp = vel_pair<S, W>(d, w, i);
+            if (vp.ok_a) {
+                const bool valid = slot ? vp.ok_b : vp.ok_a;
                 // per-velocity constants: scalar loads for both slots, lane select
-                const double x = pick<S>(slot, ldc(xv, va), ldc(xv, vb));
-                const double pk = pick<S>(slot, ldc(pv, va), ldc(pv, vb));
+                const double x = pick<S>(slot, ldc(xv, vp.va), ldc(xv, vp.vb));
+                const double pk = pick<S>(slot, ldc(pv, vp.va), ldc(pv, vp.vb));
                 double fc = (double)ra[i];
                 double h = (double)rh[i];
                 if (eqbc) {
-                    const double gl = pick<S>(slot, ldc(d.feqL, va), ldc(d.feqL, vb));
-                    const double gr = pick<S>(slot, ldc(d.feqR, va), ldc(d.feqR, vb));
+                    const double gl = pick<S>(slot, ldc(d.feqL, vp.va), ldc(d.feqL, vp.vb));
+                    const double gr = pick<S>(slot, ldc(d.feqR, vp.va), ldc(d.feqR, vp.vb));
                     fc = ghost ? (c < 0 ? gl : gr) : fc;
                     h = hghost ? (hc < 0 ? gl : gr) : h;
                 }
@@ -168,20 +190,21 @@ __device__ __forceinline__ void stage_tile(const InstDesc& d, int tile, char* ld
         wave_lds_sync();
 #pragma unroll
         for (int i = i0; i < i0 + G && i < NV; ++i) {
-            const int va = w + i * VS;
-            if (va < V) {
-                const int vb = min(va + W, V - 1);
-                const double x = pick<S>(slot, ldc(xv, va), ldc(xv, vb));
+            const VelPair vp = vel_pair<S, W>(d, w, i);
+            if (vp.ok_a) {
+                const double xa = ldc(xv, vp.va), xb = ldc(xv, vp.vb);
+                const double x = pick<S>(slot, xa, xb);
                 const Tf* wb = win + (((i0 / G) & 1) * G + (i - i0)) * S * WN;
                 double sv[6];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) sv[q] = (double)wb[cl + q];
-                double F;
-                if (S == 1) {
-                    F = 0.0;
-                    if (x > 0.0) F = x * weno5(sv[0], sv[1], sv[2], sv[3], sv[4]);
-                    else if (x < 0.0) F = x * weno5(sv[5], sv[4], sv[3], sv[2], sv[1]);
-                } else {   // the two slots may move in opposite directions: select the upwind order
+                // both slots move the same way unless the pair straddles xi = 0
+                const bool same = S == 1 || !vp.ok_b || ((xa > 0.0) == (xb > 0.0) && (xa < 0.0) == (xb < 0.0));
+                double F = 0.0;
+                if (same) {
+                    if (xa > 0.0) F = x * weno5(sv[0], sv[1], sv[2], sv[3], sv[4]);
+                    else if (xa < 0.0) F = x * weno5(sv[5], sv[4], sv[3], sv[2], sv[1]);
+                } else {
                     const bool up = x > 0.0;
                     F = x * weno5(up ? sv[0] : sv[5], up ? sv[1] : sv[4], up ? sv[2] : sv[3], up ? sv[3] : sv[2],
                                   up ? sv[4] : sv[1]);
@@ -200,7 +223,10 @@ __device__ __forceinline__ void stage_tile(const InstDesc& d, int tile, char* ld
     constexpr bool kEarlyFn = TW == 64 && NV * sizeof(Tf) <= 32 * sizeof(double);
     if (STAGE > 1 && kEarlyFn) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) rn[i] = fn[(size_t)min(vel_of(i), V - 1) * pitch + cc];
+        for (int i = 0; i < NV; ++i) {
+            const VelPair vp = vel_pair<S, W>(d, w, i);
+            rn[i] = fn[(size_t)(slot ? vp.vb : vp.va) * pitch + cc];
+        }
     }
 
     // ---- moments of the VS streams, then per-cell coefficients by wave 0
@@ -249,7 +275,10 @@ __device__ __forceinline__ void stage_tile(const InstDesc& d, int tile, char* ld
     // ---- phase 2: f_n, equilibrium, AW relaxation, RK combination, store
     if (STAGE > 1 && !kEarlyFn) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) rn[i] = fn[(size_t)min(vel_of(i), V - 1) * pitch + cc];
+        for (int i = 0; i < NV; ++i) {
+            const VelPair vp = vel_pair<S, W>(d, w, i);
+            rn[i] = fn[(size_t)(slot ? vp.vb : vp.va) * pitch + cc];
+        }
     }
     double cA = 0.0, cB = 0.0, c0[kMaxNOm + 1], c1[kMaxNOm + 1];
     if (collide) {
@@ -265,20 +294,20 @@ __device__ __forceinline__ void stage_tile(const InstDesc& d, int tile, char* ld
     const bool out_lane = !ghost && cl >= 1;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-        const int va = w + i * VS;
-        if (va < V) {
-            const int v = vel_of(i);
-            const int vb = min(va + W, V - 1);
+        const VelPair vp = vel_pair<S, W>(d, w, i);
+        if (vp.ok_a) {
+            const int v = slot ? vp.vb : vp.va;
+            const bool valid = slot ? vp.ok_b : vp.ok_a;
             double y = (double)yv[i];
             if (collide) {
-                const double l1 = pick<S>(slot, ldc(d.tab.l1v, va), ldc(d.tab.l1v, vb));
-                const double wx = pick<S>(slot, ldc(d.tab.wxw, va), ldc(d.tab.wxw, vb));
-                const double x = pick<S>(slot, ldc(xv, va), ldc(xv, vb));
+                const double l1 = pick<S>(slot, ldc(d.tab.l1v, vp.va), ldc(d.tab.l1v, vp.vb));
+                const double wx = pick<S>(slot, ldc(d.tab.wxw, vp.va), ldc(d.tab.wxw, vp.vb));
+                const double x = pick<S>(slot, ldc(xv, vp.va), ldc(xv, vp.vb));
                 double gsum = 0.0;
 #pragma unroll
                 for (int m = 0; m <= kMaxNOm; ++m)
                     if (m <= d.NOm) {
-                        const double P = pick<S>(slot, ldc(d.tab.Pv, m * V + va), ldc(d.tab.Pv, m * V + vb));
+                        const double P = pick<S>(slot, ldc(d.tab.Pv, m * V + vp.va), ldc(d.tab.Pv, m * V + vp.vb));
                         gsum = fma(P, fma(l1, c1[m], c0[m]), gsum);
                     }
                 y += dt * (cA - cB * x) * (wx * gsum - (double)fcv[i]);
@@ -287,7 +316,7 @@ __device__ __forceinline__ void stage_tile(const InstDesc& d, int tile, char* ld
             if (STAGE == 1) out = y;
             else if (STAGE == 2) out = 0.75 * (double)rn[i] + 0.25 * y;
             else out = (double)rn[i] / 3.0 + 2.0 * y / 3.0;
-            if (out_lane && v < V) {
+            if (out_lane && valid) {
                 const Tf o = (Tf)out;
                 if (!isfinite((double)o)) bad |= 2u;
                 fout[(size_t)v * pitch + c] = o;

@@ -207,6 +207,7 @@ _sig("rsl_batch_init", ctypes.c_int, [_vp, _vp, _vp, _vp])
 _sig("rsl_batch_step", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_stage", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_graph_step", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
+_sig("rsl_batch_set_path", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("rsl_batch_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("rsl_batch_status", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)])
 
@@ -246,6 +247,10 @@ class Batch:
         f, w = self._ptrs()
         check(_lib.rsl_batch_graph_step(self._h, f, w, int(nsteps), _stream(stream)))
 
+    def set_path(self, path):
+        """Bjorken batches: -1 automatic, 0 vector units, 1 matrix cores."""
+        check(_lib.rsl_batch_set_path(self._h, int(path)))
+
     def stage(self, s, stream=None):
         f, w = self._ptrs()
         check(_lib.rsl_batch_stage(self._h, f, w, int(s), _stream(stream)))
@@ -284,3 +289,104 @@ class Batch:
         if h and _lib is not None:
             _lib.rsl_batch_free(h)
             self._h = None
+
+
+_u16p = ctypes.c_void_p
+_sig("rsl_mlp_features", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, ctypes.c_double, _vp, _vp])
+_sig("rsl_mlp_to_bf16", ctypes.c_int, [_vp, _vp, _vp])
+_sig("rsl_mlp_forward", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp])
+_sig("rsl_mlp_backward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp])
+_sig("rsl_mlp_adam", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, _vp])
+_sig("rsl_mlp_tmunu", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp])
+_sig("rsl_mlp_guard", ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp])
+
+MLP_SHAPES = (("W1", (81, 128)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)), ("W3", (128, 3)), ("b3", (3,)))
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class MLP:
+    """The learned correction network: fp32 master parameters, bf16 compute copy
+    and Adam state on the GPU (layout of rsl.h)."""
+
+    def __init__(self, params=None, device="cuda"):
+        n = C["RSL_MLP_NPARAM"]
+        self.params = torch.zeros(n, dtype=torch.float32, device=device)
+        if params is not None:
+            self.params.copy_(torch.as_tensor(params, dtype=torch.float32))
+        self.pb = torch.zeros(n, dtype=torch.int16, device=device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.step_count = 0
+        self.refresh()
+
+    def refresh(self, stream=None):
+        check(_lib.rsl_mlp_to_bf16(_p(self.params), _p(self.pb), _stream(stream)))
+
+    def forward(self, x, keep=False, stream=None):
+        n = x.shape[0]
+        y = torch.empty((n, 3), dtype=torch.float32, device=x.device)
+        h1 = h2 = None
+        if keep:
+            h1 = torch.empty((n, 128), dtype=torch.int16, device=x.device)
+            h2 = torch.empty((n, 128), dtype=torch.int16, device=x.device)
+        check(_lib.rsl_mlp_forward(_p(self.pb), _p(x), n, _p(y), _p(h1), _p(h2), _stream(stream)))
+        return (y, h1, h2) if keep else y
+
+    def backward(self, x, h1, h2, y, t, stream=None):
+        check(_lib.rsl_mlp_backward(_p(self.pb), _p(x), _p(h1), _p(h2), _p(y), _p(t), x.shape[0], _p(self.grad),
+                                    _stream(stream)))
+        return self.grad
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        self.step_count += 1
+        check(_lib.rsl_mlp_adam(_p(self.params), _p(self.grad), _p(self.m), _p(self.v), _p(self.pb),
+                                self.step_count, lr, b1, b2, eps, _stream(stream)))
+
+    def unpack(self):
+        """dict of numpy arrays in the oracle's naming (fp32 master copy)."""
+        import numpy as np
+        flat = self.params.cpu().numpy().astype(np.float64)
+        out, o = {}, 0
+        for name, shp in MLP_SHAPES:
+            k = int(np.prod(shp))
+            out[name] = flat[o:o + k].reshape(shp)
+            o += k
+        return out
+
+    @staticmethod
+    def pack(P):
+        import numpy as np
+        return np.concatenate([np.asarray(P[name], dtype=np.float64).ravel() for name, _ in MLP_SHAPES])
+
+
+def features(quad, problem, f_buf, log_tau, stream=None):
+    """[nz, 81] fp32 features of one Sod instance's state buffer."""
+    out = torch.empty((problem.nz, 81), dtype=torch.float32, device=f_buf.device)
+    check(_lib.rsl_mlp_features(quad.handle, ctypes.byref(problem), _p(f_buf), float(log_tau), _p(out),
+                                _stream(stream)))
+    return out
+
+
+def tmunu_targets(m_lo, m_hi, stream=None):
+    n = m_lo.shape[0]
+    t = torch.empty((n, 3), dtype=torch.float32, device=m_lo.device)
+    check(_lib.rsl_mlp_tmunu(_p(m_lo), _p(m_hi), None, n, 0, _p(t), None, _stream(stream)))
+    return t
+
+
+def tmunu_correct(m_lo, y, stream=None):
+    n = m_lo.shape[0]
+    out = torch.empty((n, 3), dtype=torch.float64, device=m_lo.device)
+    check(_lib.rsl_mlp_tmunu(_p(m_lo), None, _p(y), n, 1, None, _p(out), _stream(stream)))
+    return out
+
+
+def guard(x, lo, hi, stream=None):
+    flag = torch.zeros(1, dtype=torch.int32, device=x.device)
+    check(_lib.rsl_mlp_guard(_p(x), x.shape[0], _p(lo), _p(hi), _p(flag), _stream(stream)))
+    return int(flag.item()) != 0

@@ -90,6 +90,7 @@ def test_bjorken_batch_equals_single(rsl):
         probs.append(rsl.make_problem(kind="bjorken", tau_mode="etas", tau_aw0=taw0))
         dts.append(1e-3)
     B = rsl.Batch(quads, probs, dts)
+    B.set_path(0)          # the per-instance kernel shares the single-instance code
     B.init()
     B.step(200)
     for i, (q, p) in enumerate(zip(quads, probs)):
@@ -125,3 +126,62 @@ def test_graph_replay_equals_eager(rsl):
                 assert torch.equal(A.f(i), B.f(i)), (rep, i)
             assert float(junk) == float(junk)
         assert B.time(0) == pytest.approx(12 * dts[0], rel=1e-14)
+
+
+def _bj_ensemble(rsl, n, seed, dtype="f64", Qs=(20, 37, 64, 200)):
+    rng = np.random.default_rng(seed)
+    quads = {Q: rsl.Quadrature(3, Q, 4) for Q in Qs}
+    qs, probs, dts = [], [], []
+    for i in range(n):
+        Q = int(rng.choice(Qs))
+        es = float(np.exp(rng.uniform(np.log(0.01), np.log(10.0))))
+        T0 = float(np.exp(rng.uniform(np.log(0.5), np.log(2.0))))
+        taw0 = 5 * 0.1973269804 * es / (0.25 * T0)
+        gas, mode = [("ideal", "etas"), ("parton", "etas"), ("ideal", "inf"), ("ideal", "const")][i % 4]
+        qs.append(quads[Q])
+        probs.append(rsl.make_problem(kind="bjorken", gas=gas, tau_mode=mode, tau_aw0=taw0, tau_r=0.3, dtype=dtype))
+        dts.append(1e-3)
+    return qs, probs, dts
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_bjorken_matrix_cores_match_vector_path(rsl, dtype, tol):
+    """The matrix-core group kernel (K^P F by MFMA f64 16x16x4) agrees with the
+    per-instance vector kernel (itself at 1e-12 of the oracle) to rounding;
+    groups are ragged (fewer than 16 instances, Q_xi not a multiple of 16)."""
+    qs, probs, dts = _bj_ensemble(rsl, 37, seed=5, dtype=dtype)
+    A = rsl.Batch(qs, probs, dts)
+    B = rsl.Batch(qs, probs, dts)
+    A.set_path(0)
+    B.set_path(1)
+    A.init()
+    B.init()
+    A.step(150)
+    B.step(150)
+    B.step(50)
+    A.step(50)
+    torch.cuda.synchronize()
+    for i in range(len(probs)):
+        a = A.f(i).double().cpu().numpy()
+        b = B.f(i).double().cpu().numpy()
+        assert np.max(np.abs(a - b)) / np.max(np.abs(a)) < tol, i
+        assert B.time(i) == pytest.approx(1.2, abs=1e-12)
+    rc, bad = B.status()
+    assert rc == 0
+
+
+def test_bjorken_matrix_cores_vs_oracle(rsl):
+    import oracle
+    qs, probs, dts = _bj_ensemble(rsl, 5, seed=8, Qs=(40, 101))
+    B = rsl.Batch(qs, probs, dts)
+    B.set_path(1)
+    B.init()
+    B.step(400)
+    for i in range(len(probs)):
+        q, p = qs[i], probs[i]
+        vs = oracle.VelocitySet(3, q.Q, 4)
+        Bo = oracle.Bjorken(vs, gas=oracle.GAS_IDEAL if p.gas == 0 else oracle.GAS_PARTON,
+                            tau_mode=p.tau_mode, tau_r=p.tau_r, tau_aw0=p.tau_aw0)
+        ref, _ = Bo.run(Bo.init(), 1.0, 1e-3, 400)
+        got = B.f(i).cpu().numpy().reshape(-1)
+        assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-12, i
