@@ -12,6 +12,7 @@ RK stage).
 Prints one JSON line (see the repository's measurement contract).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +29,11 @@ NOM = 4
 BYTES_PER_CELL_VEL_STEP = {"f64": 64, "f32": 32}   # f_n read 3x, stage fields read 2x, written 3x
 HBM_PEAK_GBS = 8000.0
 CHUNK = 10          # RK3 steps per captured HIP graph
+# HBM bytes per stage launch group read from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# counters (scaled by a plain copy kernel's readings); valid only for the
+# kernel sources and variants they were taken with
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sod_stage_c2_traffic.txt")
+KERNEL_SOURCES = ("sod_stage.h", "sod_stage_f64.hip", "sod_stage_f32.hip", "rsl_math.h", "rsl_impl.h")
 
 
 def parse():
@@ -37,6 +43,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--dtype", default="f64", choices=("f64", "f32"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default stage-kernel variants")
+    ap.add_argument("--variants", default=None,
+                    help="comma-separated stage-kernel variant per velocity class (-1: empty); skips the autotuner")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy five times (the reference kernel for "
+                         "scaling FETCH_SIZE / WRITE_SIZE counters to bytes)")
     return ap.parse_args()
 
 
@@ -54,27 +66,62 @@ def build_batch(rsl, dtype):
     return B
 
 
-def kernel_roofline(torch, B, dtype, updates_per_step, reps=20):
-    """Average duration of the batched stage kernel (all three RK stages),
-    measured with HIP events on the stream the kernels are launched on."""
-    stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * 3 * reps)]
-    k = 0
-    for _ in range(reps):
-        for s in (1, 2, 3):
-            ev[k].record(stream)
-            B.stage(s)
-            ev[k + 1].record(stream)
-            k += 2
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1612_01287_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(dtype, variants):
+    """HBM bytes per stage launch group from the committed counter summary, or
+    None when it was taken on other kernel sources or variants."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    key = "bytes_per_stage_group_" + dtype
+    if rec.get("kernel_source_hash") != kernel_source_hash() or key not in rec:
+        return None
+    if rec.get("kernel_forms_" + dtype) != kernel_forms(variants):
+        return None
+    return float(rec[key])
+
+
+def kernel_forms(variants):
+    """Per class: 's' for the two-kernel form (its HBM traffic does not depend on
+    the velocity slicing), else the fused variant id; '-' for an empty class."""
+    from paper_1612_01287_amd import rsl
+    shapes = rsl.stage_variants()
+    return ",".join("-" if v < 0 else ("s" if shapes[v][4] else str(v)) for v in variants)
+
+
+def kernel_roofline(torch, B, dtype, updates_per_step, variants, chunk, stream, reps=10):
+    """Average duration of one RK stage of the whole batch (a stage launch
+    group: the stage kernels of every velocity class, launched concurrently
+    from one stream), from HIP events on that stream around graph replays of
+    `chunk` steps (3 chunk stage groups each)."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+    for r in range(reps):
+        ev[2 * r].record(stream)
+        B.graph_step(chunk, stream=stream)
+        ev[2 * r + 1].record(stream)
     ev[-1].synchronize()
-    ms = sum(ev[i].elapsed_time(ev[i + 1]) for i in range(0, len(ev), 2)) / (3 * reps)
+    ms = sum(ev[i].elapsed_time(ev[i + 1]) for i in range(0, len(ev), 2)) / (3 * chunk * reps)
     cell_vel = updates_per_step / 3
     bytes_per_launch = BYTES_PER_CELL_VEL_STEP[dtype] / 3.0 * cell_vel
     gbs = bytes_per_launch / (ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
-                kernel="sod_batch_stage_kernel (mean of the three RK stages)", avg_launch_us=round(ms * 1e3, 2),
-                bytes_per_launch=bytes_per_launch)
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=measured_traffic(dtype, variants),
+                kernel="Sod stage launch group (one RK stage of all velocity classes; mean over %d graph-replayed "
+                       "stages)" % (3 * chunk * reps), avg_launch_us=round(ms * 1e3, 2),
+                bytes_per_launch=bytes_per_launch, variants=variants, kernel_forms=kernel_forms(variants),
+                kernel_source_hash=kernel_source_hash())
 
 
 def cpu_baseline(dtype, budget_s=15.0):
@@ -100,6 +147,16 @@ def cpu_baseline(dtype, budget_s=15.0):
                        "(single-threaded plain C)" % steps)
 
 
+def copy_calibration(torch):
+    n = 256 * 1024 * 1024 // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_copy": n * 8, "copies": 5}))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -107,12 +164,22 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_1612_01287_amd import rsl
     torch.cuda.set_device(0)
+    if a.copy_calibration:
+        copy_calibration(torch)
+        return
+    from paper_1612_01287_amd import rsl
     B = build_batch(rsl, a.dtype)
     stream = torch.cuda.Stream()          # graph replay needs an explicit stream
     chunk = max(1, min(CHUNK, a.steps))
     with torch.cuda.stream(stream):
+        if a.variants:
+            for c, v in enumerate(int(x) for x in a.variants.split(",")):
+                if v >= 0 and B.variant(c)[0] >= 0:
+                    B.set_variant(c, v)
+        elif not a.no_autotune:
+            B.autotune(reps=5, stream=stream)
+        variants = [B.variant(c)[0] for c in range(rsl.N_CLASSES)]
         for _ in range(max(1, a.warmup // chunk)):
             B.graph_step(chunk)           # first call captures the graph of `chunk` steps
         torch.cuda.synchronize()
@@ -129,7 +196,7 @@ def main():
     updates_per_step = sum(3 * NZ * q.V for q in B.quads)
     value = updates_per_step * a.steps / el
     with torch.cuda.stream(stream):
-        roof = kernel_roofline(torch, B, a.dtype, updates_per_step)
+        roof = kernel_roofline(torch, B, a.dtype, updates_per_step, variants, chunk, stream)
     out = {
         "metric": "distribution updates/s (cells x velocities x RK stages)",
         "value": value,

@@ -202,6 +202,34 @@ int rsl_batch_moments(rsl_batch* b, const void* f_dev, void* work_dev, double* o
  * LDS), 0 one workgroup per instance on the vector units, 1 matrix cores
  * (RSL_EUNSUPPORTED if not available).  The two paths agree to rounding. */
 int rsl_batch_set_path(rsl_batch* b, int path);
+/* Stage-kernel variants.  One Sod RK3 stage (Sec. III F-G: moments, Landau
+ * frame, f^eq, AW relaxation, WENO5 fluxes, RK combination) runs either as
+ * one fused kernel per tile of cells or in a two-kernel form (a per-cell
+ * kernel for the moments and equilibrium coefficients, then a kernel per
+ * (cell, velocity) for fluxes, relaxation and the RK combination).  The fused
+ * kernel has launch shapes of W waves per workgroup, NV velocities per lane
+ * and 64/TW velocity slots per wave of TW lanes (tiles of TW - 1 cells) and
+ * covers V <= W (64/TW) NV; the two-kernel form takes any V (up to 65536),
+ * its stream kernel W waves of NV velocities each and its cell kernel
+ * cell_waves waves per 63 cells.  Variants differ only in the order of
+ * the per-cell moment sums, so results agree to rounding.
+ * rsl_stage_variant returns the shape of variant id var, *max_v its largest
+ * V and *cell_waves the waves of the two-kernel form's cell kernel (0 for the
+ * fused kernel); RSL_EINVAL past the last id.
+ * A Sod batch sorts its instances into seven classes by V (V <= 32, 64, 128,
+ * 256, 320, 384 and V > 384); rsl_batch_variant reports a class's variant (-1
+ * if the class is empty) and its largest V; rsl_batch_set_variant selects one
+ * (var < 0: the default; RSL_EINVAL if it holds fewer than the class's
+ * largest V).  rsl_batch_autotune times every variant that fits each class on
+ * stage 2 (reps launches each, after one stage-1 launch; f is left
+ * unchanged, the work buffer's stage fields are overwritten), keeps the
+ * fastest and writes the chosen ids to chosen[7] (if not NULL; -1 for empty
+ * classes).  It synchronises the stream.  Changing a variant drops the
+ * captured graph. */
+int rsl_stage_variant(int var, int* waves, int* vel_per_slot, int* lanes_per_vel, int* max_v, int* cell_waves);
+int rsl_batch_variant(const rsl_batch* b, int cls, int* var, int* max_v);
+int rsl_batch_set_variant(rsl_batch* b, int cls, int var);
+int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void* hip_stream, int* chosen);
 /* Synchronises and reads every instance's status word; *first_bad (if not
  * NULL) receives the first failing instance or -1. */
 int rsl_batch_status(rsl_batch* b, void* work_dev, void* hip_stream, int* first_bad);
@@ -222,9 +250,11 @@ int rsl_batch_status(rsl_batch* b, void* work_dev, void* hip_stream, int* first_
 #define RSL_MLP_OUT     3
 #define RSL_MLP_NPARAM  27395
 
-/* feat_dev[nz][81] (fp32) from one Sod instance's f. */
-int rsl_mlp_features(const rsl_quad* q, const rsl_problem* p, const void* f_dev, double log_tau, float* feat_dev,
-                     void* hip_stream);
+/* feat_dev[nz][81] (fp32) from one Sod instance's f.  With shift_dev and
+ * scale_dev (device [81], both or neither) each feature x is stored as
+ * (x - shift) / scale in fp32 (the standardisation a trained network expects). */
+int rsl_mlp_features(const rsl_quad* q, const rsl_problem* p, const void* f_dev, double log_tau,
+                     const float* shift_dev, const float* scale_dev, float* feat_dev, void* hip_stream);
 /* bf16 (round to nearest even) copy of fp32 parameters. */
 int rsl_mlp_to_bf16(const float* params, unsigned short* params_bf16, void* hip_stream);
 /* y[n][3] = net(x[n][81]).  h1, h2 ([n][128] bf16 each) receive the hidden

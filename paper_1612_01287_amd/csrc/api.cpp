@@ -38,7 +38,8 @@ WorkLayout work_layout(const rsl_quad* q, const rsl_problem* p) {
     L.feqL_off = 2 * L.f_bytes;
     L.feqR_off = L.feqL_off + align_up(sizeof(double) * q->V, 256);
     L.status_off = L.feqR_off + align_up(sizeof(double) * q->V, 256);
-    L.total = L.status_off + 256;
+    L.cell_off = L.status_off + 256;
+    L.total = L.cell_off + (p->problem == RSL_SOD ? sizeof(double) * kCellPar * pitch : 0);
     return L;
 }
 
@@ -73,6 +74,7 @@ InstDesc make_desc(const rsl_quad* q, const rsl_problem* p, void* f, void* work,
     d.feqR = (const double*)(w + L.feqR_off);
     d.status = (unsigned*)(w + L.status_off);
     d.clock = (double*)(w + L.status_off + 8);
+    d.cell = (double*)(w + L.cell_off);
     return d;
 }
 

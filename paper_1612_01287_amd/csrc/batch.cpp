@@ -54,7 +54,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // the per-cell work (Landau frame, equilibrium coefficients) is ~25 updates.
 double tile_cost(const rsl_quad* q) { return (double)kLanes * (q->V + 25.0); }
 
-std::vector<int2> schedule(const rsl_batch* b, int cls) {
+std::vector<int2> schedule(const rsl_batch* b, int cls, int tc) {
     const int X = 8;
     std::vector<int> order;
     for (int i = 0; i < b->n; ++i)
@@ -64,7 +64,6 @@ std::vector<int2> schedule(const rsl_batch* b, int cls) {
     std::vector<std::vector<std::pair<double, int2>>> q(X);
     std::vector<double> load(X, 0.0);
     for (int i : order) {
-        const int tc = stage_tile_cells(cls);
         const int nt = (b->probs[i].nz + tc - 1) / tc;
         const double c = tile_cost(b->quads[i]) * tc / kTileCells;
         const int run = std::max(1, (nt + X - 1) / X);
@@ -108,8 +107,20 @@ std::vector<int> bj_groups(const rsl_batch* b) {
     return g;
 }
 
+// Tile widths of the stage kernel variants: index 0 -> 63 cells, 1 -> 31 cells.
+constexpr int kTileWidths[2] = {63, 31};
+
+int tw_index(int var) { return stage_variant_tile_cells(var) == kTileWidths[0] ? 0 : 1; }
+
+void use_variant(StageClass& cl, int var) {
+    cl.var = var;
+    const int t = tw_index(var);
+    cl.items = cl.items_tw[t];
+    cl.nitems = cl.nitems_tw[t];
+}
+
 int batch_upload(rsl_batch* b) {
-    std::vector<std::vector<int2>> items(kClasses);
+    std::vector<std::vector<int2>> items(2 * kClasses);
     size_t total = 0;
     std::vector<int> groups;
     if (b->kind == RSL_BJORKEN) {
@@ -125,10 +136,11 @@ int batch_upload(rsl_batch* b) {
         }
     }
     if (b->kind == RSL_SOD)
-        for (int c = 0; c < kClasses; ++c) {
-            items[c] = schedule(b, c);
-            total += align_up(sizeof(int2) * items[c].size(), 256);
-        }
+        for (int c = 0; c < kClasses; ++c)
+            for (int t = 0; t < 2; ++t) {
+                items[2 * c + t] = schedule(b, c, kTileWidths[t]);
+                total += align_up(sizeof(int2) * items[2 * c + t].size(), 256);
+            }
     const size_t dbytes = align_up(sizeof(InstDesc) * b->n, 256);
     int rc = hip_check(hipMalloc(&b->dmem, dbytes + std::max<size_t>(total, 256)), "hipMalloc(batch)");
     if (rc) return rc;
@@ -137,14 +149,20 @@ int batch_upload(rsl_batch* b) {
     size_t off = dbytes;
     for (int c = 0; c < kClasses && rc == RSL_OK; ++c) {
         StageClass& cl = b->launch.cl[c];
-        cl.cls = c;
         cl.descs = (const InstDesc*)b->dmem;
-        cl.items = (const int2*)((char*)b->dmem + off);
-        cl.nitems = (int)items[c].size();
-        if (cl.nitems)
-            rc = hip_check(hipMemcpy((char*)b->dmem + off, items[c].data(), sizeof(int2) * items[c].size(),
-                                     hipMemcpyHostToDevice), "hipMemcpy(batch items)");
-        off += align_up(sizeof(int2) * items[c].size(), 256);
+        cl.maxV = 0;
+        for (int i = 0; i < b->n; ++i)
+            if (b->kind == RSL_SOD && stage_class_of(b->quads[i]->V) == c) cl.maxV = std::max(cl.maxV, b->quads[i]->V);
+        for (int t = 0; t < 2 && rc == RSL_OK; ++t) {
+            const std::vector<int2>& it = items[2 * c + t];
+            cl.items_tw[t] = (const int2*)((char*)b->dmem + off);
+            cl.nitems_tw[t] = (int)it.size();
+            if (!it.empty())
+                rc = hip_check(hipMemcpy((char*)b->dmem + off, it.data(), sizeof(int2) * it.size(),
+                                         hipMemcpyHostToDevice), "hipMemcpy(batch items)");
+            off += align_up(sizeof(int2) * it.size(), 256);
+        }
+        use_variant(cl, stage_default_variant(c));
     }
     if (rc == RSL_OK && !groups.empty()) {
         b->groups = (int*)((char*)b->dmem + off);
@@ -381,6 +399,84 @@ int rsl_batch_set_path(rsl_batch* b, int path) {
     b->bj_path = path;
     batch_drop_graph(b);
     return RSL_OK;
+}
+
+int rsl_stage_variant(int var, int* waves, int* vel_per_slot, int* lanes_per_vel, int* max_v, int* cell_waves) {
+    int W, NV, TW, WC;
+    bool split;
+    if (!stage_variant_shape(var, &W, &NV, &TW, &split, &WC))
+        return set_error(RSL_EINVAL, "unknown stage kernel variant");
+    if (waves) *waves = W;
+    if (vel_per_slot) *vel_per_slot = NV;
+    if (lanes_per_vel) *lanes_per_vel = TW;
+    if (max_v) *max_v = stage_variant_capacity(var);
+    if (cell_waves) *cell_waves = WC;
+    return RSL_OK;
+}
+
+int rsl_batch_variant(const rsl_batch* b, int cls, int* var, int* max_v) {
+    if (!b || cls < 0 || cls >= kClasses) return set_error(RSL_EINVAL, "bad batch class");
+    const StageClass& cl = b->launch.cl[cls];
+    if (var) *var = cl.nitems ? cl.var : -1;
+    if (max_v) *max_v = cl.maxV;
+    return RSL_OK;
+}
+
+int rsl_batch_set_variant(rsl_batch* b, int cls, int var) {
+    if (!b || cls < 0 || cls >= kClasses) return set_error(RSL_EINVAL, "bad batch class");
+    if (b->kind != RSL_SOD) return set_error(RSL_EINVAL, "kernel variants exist for Sod batches only");
+    StageClass& cl = b->launch.cl[cls];
+    if (var < 0) var = stage_default_variant(cls);
+    const int cap = stage_variant_capacity(var);
+    if (cap == 0) return set_error(RSL_EINVAL, "unknown stage kernel variant");
+    if (cap < cl.maxV) return set_error(RSL_EINVAL, "variant holds fewer velocities than the class needs");
+    use_variant(cl, var);
+    batch_drop_graph(b);
+    return RSL_OK;
+}
+
+int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void* hip_stream, int* chosen) {
+    if (!b || !f_dev || !work_dev) return set_error(RSL_EINVAL, "null argument");
+    if (b->kind != RSL_SOD) return set_error(RSL_EINVAL, "kernel variants exist for Sod batches only");
+    if (reps <= 0) return set_error(RSL_EINVAL, "reps must be > 0");
+    hipStream_t s = (hipStream_t)hip_stream;
+    char* f = (char*)f_dev;
+    char* w = (char*)work_dev;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = hip_check(hipEventCreate(&e0), "hipEventCreate");
+    if (rc == RSL_OK) rc = hip_check(hipEventCreate(&e1), "hipEventCreate");
+    for (int c = 0; c < kClasses && rc == RSL_OK; ++c) {
+        StageClass& cl = b->launch.cl[c];
+        if (chosen) chosen[c] = -1;
+        if (!cl.nitems) continue;
+        // stage 1 once, so that stage 2 (which reads f and f^(1) and writes
+        // only f^(2) and the status word) can be repeated on valid data
+        use_variant(cl, stage_default_variant(c));
+        rc = launch_sod_class_stage(cl, b->dtype, 1, f, w, s);
+        int best = cl.var;
+        float best_ms = 1e30f;
+        for (int v = 0; rc == RSL_OK && stage_variant_capacity(v) > 0; ++v) {
+            if (stage_variant_capacity(v) < cl.maxV) continue;
+            use_variant(cl, v);
+            rc = launch_sod_class_stage(cl, b->dtype, 2, f, w, s);
+            if (rc == RSL_OK) rc = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+            for (int r = 0; r < reps && rc == RSL_OK; ++r) rc = launch_sod_class_stage(cl, b->dtype, 2, f, w, s);
+            if (rc == RSL_OK) rc = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+            if (rc == RSL_OK) rc = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.0f;
+            if (rc == RSL_OK) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (rc == RSL_OK && ms < best_ms) {
+                best_ms = ms;
+                best = v;
+            }
+        }
+        use_variant(cl, best);
+        if (chosen) chosen[c] = best;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    batch_drop_graph(b);
+    return rc;
 }
 
 int rsl_batch_status(rsl_batch* b, void* work_dev, void* hip_stream, int* first_bad) {

@@ -303,7 +303,8 @@ __global__ void to_bf16_kernel(const float* __restrict__ p, unsigned short* __re
 // have their moments computed once into LDS.
 template <typename Tf>
 __global__ void __launch_bounds__(TPB) features_kernel(InstDesc d, const Tf* __restrict__ f, double log_tau,
-                                                       float* __restrict__ out) {
+                                                       const float* __restrict__ shift,
+                                                       const float* __restrict__ scale, float* __restrict__ out) {
     __shared__ double Ms[(TPB + 4) * 16];
     const int s0 = blockIdx.x * TPB;
     for (int t = threadIdx.x; t < TPB + 4; t += blockDim.x) {
@@ -328,14 +329,16 @@ __global__ void __launch_bounds__(TPB) features_kernel(InstDesc d, const Tf* __r
     const double* c = Ms + (threadIdx.x + 2) * 16;
     const double n0 = c[0], e0 = c[8];
     float* o = out + (size_t)s * NI;
+    float x[NI];
     for (int off = 0; off < 5; ++off) {
         const double* m = Ms + (threadIdx.x + off) * 16;
         for (int r = 0; r < 8; ++r) {
-            o[off * 16 + r] = (float)(m[r] / n0);
-            o[off * 16 + 8 + r] = (float)(m[8 + r] / e0);
+            x[off * 16 + r] = (float)(m[r] / n0);
+            x[off * 16 + 8 + r] = (float)(m[8 + r] / e0);
         }
     }
-    o[80] = (float)log_tau;
+    x[80] = (float)log_tau;
+    for (int i = 0; i < NI; ++i) o[i] = shift ? (x[i] - shift[i]) / scale[i] : x[i];
 }
 
 // mode 0: t = (T_hi - T_lo) / T^00_lo; mode 1: T_corr = T_lo + y T^00_lo.
@@ -379,18 +382,22 @@ using namespace rsl;
 
 extern "C" {
 
-int rsl_mlp_features(const rsl_quad* q, const rsl_problem* p, const void* f_dev, double log_tau, float* feat_dev,
+int rsl_mlp_features(const rsl_quad* q, const rsl_problem* p, const void* f_dev, double log_tau,
+                     const float* shift_dev, const float* scale_dev, float* feat_dev,
                      void* hip_stream) {
     if (!q || !p || !f_dev || !feat_dev) return set_error(RSL_EINVAL, "null argument");
     if (!q->on_device) return set_error(RSL_EINVAL, "rsl_quad was built with RSL_QUAD_HOST_ONLY");
     if (p->problem != RSL_SOD) return set_error(RSL_EINVAL, "features are defined for Sod instances");
+    if (!shift_dev != !scale_dev) return set_error(RSL_EINVAL, "shift and scale go together");
     InstDesc d = make_desc(q, p, (void*)f_dev, (void*)f_dev, 0.0);
     hipStream_t s = (hipStream_t)hip_stream;
     const dim3 grid((p->nz + TPB - 1) / TPB);
     if (p->dtype == RSL_F64)
-        hipLaunchKernelGGL(features_kernel<double>, grid, dim3(TPB), 0, s, d, (const double*)f_dev, log_tau, feat_dev);
+        hipLaunchKernelGGL(features_kernel<double>, grid, dim3(TPB), 0, s, d, (const double*)f_dev, log_tau,
+                           shift_dev, scale_dev, feat_dev);
     else
-        hipLaunchKernelGGL(features_kernel<float>, grid, dim3(TPB), 0, s, d, (const float*)f_dev, log_tau, feat_dev);
+        hipLaunchKernelGGL(features_kernel<float>, grid, dim3(TPB), 0, s, d, (const float*)f_dev, log_tau,
+                           shift_dev, scale_dev, feat_dev);
     return hip_check(hipGetLastError(), "features_kernel launch");
 }
 

@@ -61,7 +61,13 @@ struct InstDesc {
     const double* feqR;  // [V] ghost state right
     unsigned* status;    // bit 0: unphysical cell state; bit 1: non-finite f
     double* clock;       // Bjorken batches: current proper time of the instance
+    double* cell;        // Sod: per-cell relaxation and equilibrium coefficients
+                         // [kCellPar][pitch] of the current stage (two-kernel stage form)
 };
+
+// Per-cell coefficients stored by the two-kernel stage form: gamma/tau,
+// gamma beta/tau, c0[0..kMaxNOm], c1[0..kMaxNOm].
+constexpr int kCellPar = 2 + 2 * (kMaxNOm + 1);
 
 // Descriptors stored by a batch hold byte offsets (f relative to the batch's f
 // buffer, the rest relative to its work buffer); kernels add the bases.
@@ -73,17 +79,27 @@ __host__ __device__ inline void rebase(InstDesc& d, char* fbase, char* wbase) {
     d.feqR = (const double*)(wbase + (size_t)d.feqR);
     d.status = (unsigned*)(wbase + (size_t)d.status);
     d.clock = (double*)(wbase + (size_t)d.clock);
+    d.cell = (double*)(wbase + (size_t)d.cell);
 }
 
-// Work items of one velocity-set class (see stage_class_of) in a batch.
+// Work items of one velocity-set class (see stage_class_of) in a batch.  The
+// class runs one kernel variant (sod_stage.h); items exist for both tile
+// widths (63 and 31 cells) so that the autotuner can switch variants.
 struct StageClass {
-    int cls;                 // kernel variant
+    int var;                 // kernel variant in use
+    int maxV;                // largest velocity set of the class
     const InstDesc* descs;   // device [n]
-    const int2* items;       // device [nitems], (instance, tile) or (-1, -1)
+    const int2* items;       // device items of the current tile width, (instance, tile) or (-1, -1)
     int nitems;
+    const int2* items_tw[2]; // [0]: 63-cell tiles, [1]: 31-cell tiles
+    int nitems_tw[2];
 };
 
-constexpr int kClasses = 6;
+// Velocity-set classes of a Sod batch: V <= 32, 64, 128, 256, 320, 384 (the
+// capacities of the fused stage kernel's shapes) and V > 384.
+constexpr int kClasses = 7;
+// Largest velocity set accepted by the Sod stage kernels.
+constexpr int kMaxVelocities = 1 << 16;
 struct BatchLaunch {
     StageClass cl[kClasses];
 };
@@ -108,7 +124,7 @@ int hip_check(hipError_t e, const char* what);
 
 // Work-buffer layout for one instance.
 struct WorkLayout {
-    size_t f_bytes, f1_off, f2_off, feqL_off, feqR_off, status_off, total;
+    size_t f_bytes, f1_off, f2_off, feqL_off, feqR_off, status_off, cell_off, total;
 };
 WorkLayout work_layout(const rsl_quad* q, const rsl_problem* p);
 InstDesc make_desc(const rsl_quad* q, const rsl_problem* p, void* f, void* work, double dt);
@@ -121,7 +137,11 @@ int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s);
 int launch_sod_moments(const InstDesc& d, const void* f, double* out, hipStream_t s);
 int launch_sod_class_stage(const StageClass& cl, int dtype, int stage, char* fbase, char* wbase, hipStream_t s);
 int stage_class_of(int V);
-int stage_tile_cells(int cls);
+int stage_default_variant(int cls);
+bool stage_variant_shape(int var, int* W, int* NV, int* TW, bool* split, int* WC);
+int stage_variant_count();
+int stage_variant_capacity(int var);
+int stage_variant_tile_cells(int var);
 int launch_bj_batch_steps(const InstDesc* descs, int n, size_t lds, int dtype, char* fbase, char* wbase,
                           double tau0, double dtau, int nsteps, hipStream_t s);
 int launch_bj_init(const InstDesc& d, double n0, double T0s, double tau0, hipStream_t s);

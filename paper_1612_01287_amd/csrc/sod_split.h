@@ -1,0 +1,299 @@
+#pragma once
+// Two-kernel form of one Sod RK3 stage (same operator as sod_stage.h).
+//
+// The fused stage kernel keeps every velocity of a tile in one workgroup so
+// that the moments never leave the chip; for large velocity sets that pins
+// many registers per lane and few waves per SIMD.  Here the stage is split
+// at the only coupling between velocities, the moments:
+//
+//   cell kernel    per cell: the five moments of the stage field (eq. macro_jk
+//                  in discrete form), the Landau frame (eqs. E_landau,
+//                  u_landau), tau (eq. Sod:tau) and the equilibrium
+//                  coefficients c0[m], c1[m], stored as kCellPar rows of the
+//                  work buffer;
+//   stream kernel  per (cell, velocity): the WENO5 fluxes (Sec. III F), the
+//                  advective update, f^eq_jk from the stored coefficients, the
+//                  AW relaxation and the RK combination (eq. rk3).
+//
+// Velocities are independent in the stream kernel, so its workgroups take
+// any slice of the velocity set: W waves x NV velocities each, over the
+// 63-cell tiles of the fused kernel; the cell kernel splits each cell's
+// velocity sum over WC waves.  The price is a second read of the stage
+// field (by then mostly in the last-level cache) and kCellPar doubles per cell.
+#include "sod_stage.h"
+
+namespace rsl {
+
+namespace {
+
+constexpr int kCellUnroll = 8;  // stage-field loads per wave in flight in the cell kernel
+
+// WC waves split the velocity sum of 63 cells (one lane per cell).
+template <typename Tf, int STAGE, int WC>
+__device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, double* red) {
+    constexpr int W = WC, U = kCellUnroll;
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    const int c = tile * kTileCells + lane;
+    const bool live = lane < kTileCells && c < d.nz;
+    const int cc = min(c, d.nz - 1);
+    const Tf* __restrict__ fcur = (const Tf*)(STAGE == 1 ? d.f : (STAGE == 2 ? d.f1 : d.f2));
+    const size_t pitch = (size_t)d.pitch;
+    const int V = d.V;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
+    for (int v0 = w; v0 < V; v0 += U * W) {
+        Tf r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) r[u] = fcur[(size_t)min(v0 + u * W, V - 1) * pitch + cc];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * W;
+            if (v < V) {
+                const double x = ldc(d.tab.xv, v), pk = ldc(d.tab.pv, v);
+                const double fo = (double)r[u];
+                const double p = pk * fo;
+                m0 += fo;
+                m1 += x * fo;
+                m2 += p;
+                m3 += x * p;
+                m4 += x * x * p;
+            }
+        }
+    }
+    red[(w * 5 + 0) * kLanes + lane] = m0;
+    red[(w * 5 + 1) * kLanes + lane] = m1;
+    red[(w * 5 + 2) * kLanes + lane] = m2;
+    red[(w * 5 + 3) * kLanes + lane] = m3;
+    red[(w * 5 + 4) * kLanes + lane] = m4;
+    __syncthreads();
+    if (w != 0 || !live) return;
+    double M[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        double sum = red[q * kLanes + lane];
+#pragma unroll
+        for (int ww = 1; ww < W; ++ww) sum += red[(ww * 5 + q) * kLanes + lane];
+        M[q] = sum;
+    }
+    CellState cs = landau(M[0], M[1], M[2], M[3], M[4]);
+    if (!cs.ok) {
+        atomicOr(d.status, 1u);
+        cs.n = 1.0; cs.T = 1.0; cs.beta = 0.0; cs.gamma = 1.0;
+    }
+    double tau = d.tau_r;
+    if (d.tau_mode == RSL_TAU_ETAS) {
+        const double lam = cs.n / (cs.T * cs.T * cs.T);
+        tau = d.tau_aw0 / cs.T * (1.0 - 0.25 * log(lam * d.lambda_ref));
+    }
+    const double it = 1.0 / tau;
+    double c0[kMaxNOm + 1], c1[kMaxNOm + 1];
+    feq_coef(cs.n, cs.T, cs.beta, cs.gamma, d.T0, d.NOm, d.beta_series, d.tab.ser, d.tab.thr, c0, c1);
+    double* out = d.cell + c;
+    out[0] = cs.gamma * it;
+    out[pitch] = cs.gamma * cs.beta * it;
+#pragma unroll
+    for (int m = 0; m <= kMaxNOm; ++m) {
+        out[(2 + m) * pitch] = c0[m];
+        out[(3 + kMaxNOm + m) * pitch] = c1[m];
+    }
+}
+
+template <typename Tf, int STAGE, int W, int NV>
+__device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp, char* lds) {
+    constexpr int G = kGroup;
+    constexpr int WN = kWin;
+    const int vbase = grp * (W * NV);
+    if (vbase >= d.V) return;            // no workgroup-wide barrier below
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    const int z0 = tile * kTileCells;
+    const int c = z0 - 1 + lane;
+    const bool ghost = (c < 0) || (c >= d.nz);
+    const int cc = min(max(c, 0), d.nz - 1);
+    const int hc = lane < 2 ? z0 - 3 + lane : z0 + kLanes - 3 + lane;
+    const bool hghost = (hc < 0) || (hc >= d.nz);
+    const int hcc = min(max(hc, 0), d.nz - 1);
+    const bool eqbc = d.bc == RSL_BC_EQ;
+    const int V = d.V;
+    Tf* win = (Tf*)lds + w * 2 * G * WN;
+
+    const Tf* __restrict__ fcur = (const Tf*)(STAGE == 1 ? d.f : (STAGE == 2 ? d.f1 : d.f2));
+    Tf* __restrict__ fout = (Tf*)(STAGE == 1 ? d.f1 : (STAGE == 2 ? d.f2 : d.f));
+    const Tf* __restrict__ fn = (const Tf*)d.f;
+    const size_t pitch = (size_t)d.pitch;
+    const double dt = d.dt, dzi = d.dz_inv;
+
+    // stage-field and f_n loads of all NV velocities in flight at once
+    Tf ra[NV], rh[NV], rn[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int v = min(vbase + w + i * W, V - 1);
+        const Tf* row = fcur + (size_t)v * pitch;
+        ra[i] = row[cc];
+        rh[i] = lane < 5 ? row[hcc] : Tf(0);
+        if (STAGE > 1) rn[i] = fn[(size_t)v * pitch + cc];
+    }
+    // the lane's cell coefficients
+    const bool collide = d.tau_mode != RSL_TAU_INF;
+    double cA = 0.0, cB = 0.0, c0[kMaxNOm + 1], c1[kMaxNOm + 1];
+#pragma unroll
+    for (int m = 0; m <= kMaxNOm; ++m) c0[m] = c1[m] = 0.0;
+    if (collide) {
+        const double* cp = d.cell + cc;
+        cA = cp[0];
+        cB = cp[pitch];
+#pragma unroll
+        for (int m = 0; m <= kMaxNOm; ++m)
+            if (m <= d.NOm) {
+                c0[m] = cp[(2 + m) * pitch];
+                c1[m] = cp[(3 + kMaxNOm + m) * pitch];
+            }
+    }
+
+    const bool out_lane = !ghost && lane >= 1;
+    unsigned bad = 0;
+#pragma unroll
+    for (int i0 = 0; i0 < NV; i0 += G) {
+        if (vbase + w + i0 * W >= V) break;
+#pragma unroll
+        for (int i = i0; i < i0 + G && i < NV; ++i) {
+            const int v = vbase + w + i * W;
+            if (v < V) {
+                double fc = (double)ra[i], h = (double)rh[i];
+                if (eqbc) {
+                    const double gl = ldc(d.feqL, v), gr = ldc(d.feqR, v);
+                    fc = ghost ? (c < 0 ? gl : gr) : fc;
+                    h = hghost ? (hc < 0 ? gl : gr) : h;
+                }
+                Tf* wb = win + (((i0 / G) & 1) * G + (i - i0)) * WN;
+                wb[lane + 2] = (Tf)fc;
+                if (lane < 2) wb[lane] = (Tf)h;
+                else if (lane < 5) wb[kLanes + lane] = (Tf)h;
+            }
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int i = i0; i < i0 + G && i < NV; ++i) {
+            const int v = vbase + w + i * W;
+            if (v < V) {
+                const double x = ldc(d.tab.xv, v);
+                const Tf* wb = win + (((i0 / G) & 1) * G + (i - i0)) * WN;
+                double sv[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) sv[q] = (double)wb[lane + q];
+                double F = 0.0;
+                if (x > 0.0) F = x * weno5(sv[0], sv[1], sv[2], sv[3], sv[4]);
+                else if (x < 0.0) F = x * weno5(sv[5], sv[4], sv[3], sv[2], sv[1]);
+                const double Fm = shift_up(F);
+                double y = (double)(Tf)(sv[2] + dt * (-(F - Fm) * dzi));
+                if (collide) {
+                    const double l1 = ldc(d.tab.l1v, v), wx = ldc(d.tab.wxw, v);
+                    double gsum = 0.0;
+#pragma unroll
+                    for (int m = 0; m <= kMaxNOm; ++m)
+                        if (m <= d.NOm) gsum = fma(ldc(d.tab.Pv, m * V + v), fma(l1, c1[m], c0[m]), gsum);
+                    y += dt * (cA - cB * x) * (wx * gsum - sv[2]);
+                }
+                double out;
+                if (STAGE == 1) out = y;
+                else if (STAGE == 2) out = 0.75 * (double)rn[i] + 0.25 * y;
+                else out = (double)rn[i] / 3.0 + 2.0 * y / 3.0;
+                if (out_lane) {
+                    const Tf o = (Tf)out;
+                    if (!isfinite((double)o)) bad |= 2u;
+                    fout[(size_t)v * pitch + c] = o;
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(d.status, bad);
+}
+
+template <typename Tf, int STAGE, int WC>
+__global__ void __launch_bounds__(WC * 64) cell_single_kernel(InstDesc d, int ntiles) {
+    __shared__ double red[WC * 5 * kLanes];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles || d.tau_mode == RSL_TAU_INF) return;
+    cell_tile<Tf, STAGE, WC>(d, tile, red);
+}
+
+template <typename Tf, int STAGE, int WC>
+__global__ void __launch_bounds__(WC * 64) cell_batch_kernel(const InstDesc* __restrict__ descs,
+                                                            const int2* __restrict__ items, char* fbase,
+                                                            char* wbase) {
+    __shared__ double red[WC * 5 * kLanes];
+    const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;
+    InstDesc d = descs[it.x];
+    if (d.tau_mode == RSL_TAU_INF) return;
+    rebase(d, fbase, wbase);
+    cell_tile<Tf, STAGE, WC>(d, it.y, red);
+}
+
+template <typename Tf, int STAGE, int W, int NV>
+__global__ void __launch_bounds__(W * 64) stream_single_kernel(InstDesc d, int ntiles) {
+    __shared__ Tf win[W * 2 * kGroup * kWin];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    stream_tile<Tf, STAGE, W, NV>(d, tile, blockIdx.y, (char*)win);
+}
+
+template <typename Tf, int STAGE, int W, int NV>
+__global__ void __launch_bounds__(W * 64) stream_batch_kernel(const InstDesc* __restrict__ descs,
+                                                             const int2* __restrict__ items, char* fbase,
+                                                             char* wbase) {
+    __shared__ Tf win[W * 2 * kGroup * kWin];
+    const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;
+    InstDesc d = descs[it.x];
+    rebase(d, fbase, wbase);
+    stream_tile<Tf, STAGE, W, NV>(d, it.y, blockIdx.y, (char*)win);
+}
+
+// Two launches on one stream: the cell kernel (WC waves) over the 63-cell
+// tiles, then the stream kernel (W waves of NV velocities) over (tile,
+// velocity slice).  A batch class sizes the slice dimension by its largest V.
+template <typename Tf, int STAGE, int W, int NV, int WC>
+int launch_split_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s) {
+    if (d) {
+        const int ntiles = (d->nz + kTileCells - 1) / kTileCells;
+        const int nb = (ntiles + 7) / 8 * 8;
+        const int ng = (d->V + W * NV - 1) / (W * NV);
+        hipLaunchKernelGGL((cell_single_kernel<Tf, STAGE, WC>), dim3(nb), dim3(WC * 64), 0, s, *d, ntiles);
+        hipLaunchKernelGGL((stream_single_kernel<Tf, STAGE, W, NV>), dim3(nb, ng), dim3(W * 64), 0, s, *d, ntiles);
+    } else {
+        const int ng = (cl->maxV + W * NV - 1) / (W * NV);
+        hipLaunchKernelGGL((cell_batch_kernel<Tf, STAGE, WC>), dim3(cl->nitems), dim3(WC * 64), 0, s, cl->descs,
+                           cl->items, fb, wb);
+        hipLaunchKernelGGL((stream_batch_kernel<Tf, STAGE, W, NV>), dim3(cl->nitems, ng), dim3(W * 64), 0, s,
+                           cl->descs, cl->items, fb, wb);
+    }
+    return hip_check(hipGetLastError(), "sod two-kernel stage launch");
+}
+
+template <typename Tf, int STAGE>
+int launch_cls(int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s) {
+    switch (var) {
+#define RSL_CASE(id, W, NV, TW) \
+    case id: return launch_t<Tf, STAGE, W, NV, TW>(d, cl, fb, wb, s);
+        RSL_STAGE_VARIANTS(RSL_CASE)
+#undef RSL_CASE
+#define RSL_CASE(id, W, NV, WC) \
+    case id: return launch_split_t<Tf, STAGE, W, NV, WC>(d, cl, fb, wb, s);
+        RSL_SPLIT_VARIANTS(RSL_CASE)
+#undef RSL_CASE
+        default: return set_error(RSL_EINVAL, "unknown stage kernel variant");
+    }
+}
+
+template <typename Tf>
+int launch_stage_any(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb,
+                     hipStream_t s) {
+    if (stage == 1) return launch_cls<Tf, 1>(var, d, cl, fb, wb, s);
+    if (stage == 2) return launch_cls<Tf, 2>(var, d, cl, fb, wb, s);
+    return launch_cls<Tf, 3>(var, d, cl, fb, wb, s);
+}
+
+}  // namespace
+
+}  // namespace rsl

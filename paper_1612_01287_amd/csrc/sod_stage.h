@@ -355,6 +355,15 @@ constexpr size_t lds_bytes_t() {
 template <typename Tf, int STAGE, int W, int NV, int TW>
 int launch_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s) {
     const size_t lds = lds_bytes_t<W, TW, Tf>();
+    static_assert(lds_bytes_t<W, TW, Tf>() <= 160 * 1024, "stage kernel LDS above 160 KiB");
+    if (lds > 64 * 1024) {
+        static const hipError_t a1 = hipFuncSetAttribute((const void*)stage_single_kernel<Tf, STAGE, W, NV, TW>,
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        static const hipError_t a2 = hipFuncSetAttribute((const void*)stage_batch_kernel<Tf, STAGE, W, NV, TW>,
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (a1 != hipSuccess) return hip_check(a1, "hipFuncSetAttribute(stage kernel)");
+        if (a2 != hipSuccess) return hip_check(a2, "hipFuncSetAttribute(stage kernel)");
+    }
     if (d) {
         const int ntiles = (d->nz + TW - 2) / (TW - 1);
         const int nb = (ntiles + 7) / 8 * 8;
@@ -366,30 +375,19 @@ int launch_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStr
     return hip_check(hipGetLastError(), "sod stage kernel launch");
 }
 
-// Velocity-set classes (index = stage_class_of(V)): waves W, velocities per
-// slot NV, lanes per velocity TW (cells per tile TW - 1).
-template <typename Tf, int STAGE>
-int launch_cls(int cls, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s) {
-    switch (cls) {
-        case 0: return launch_t<Tf, STAGE, 4, 8, 64>(d, cl, fb, wb, s);
-        case 1: return launch_t<Tf, STAGE, 4, 16, 64>(d, cl, fb, wb, s);
-        case 2: return launch_t<Tf, STAGE, 8, 16, 64>(d, cl, fb, wb, s);
-        case 3: return launch_t<Tf, STAGE, 8, 16, 32>(d, cl, fb, wb, s);
-        case 4: return launch_t<Tf, STAGE, 8, 20, 32>(d, cl, fb, wb, s);
-        default: return launch_t<Tf, STAGE, 8, 24, 32>(d, cl, fb, wb, s);
-    }
-}
-
-template <typename Tf>
-int launch_stage_any(int stage, int cls, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s) {
-    if (stage == 1) return launch_cls<Tf, 1>(cls, d, cl, fb, wb, s);
-    if (stage == 2) return launch_cls<Tf, 2>(cls, d, cl, fb, wb, s);
-    return launch_cls<Tf, 3>(cls, d, cl, fb, wb, s);
-}
+// Kernel variants of the fused form: (waves W, velocities per slot NV, lanes
+// per velocity TW); a variant covers V <= W * (64 / TW) * NV velocities.
+#define RSL_STAGE_VARIANTS(X) \
+    X(0, 4, 8, 64) X(1, 8, 4, 64) X(2, 4, 16, 64) X(3, 8, 8, 64) X(4, 8, 16, 64) X(5, 16, 8, 64) \
+    X(6, 16, 4, 32) X(7, 8, 16, 32) X(8, 8, 20, 32) X(9, 8, 24, 32)
+// Variants of the two-kernel form (sod_split.h): stream-kernel waves W,
+// velocities per wave NV, cell-kernel waves WC; any V.
+#define RSL_SPLIT_VARIANTS(X) \
+    X(10, 4, 2, 8) X(11, 4, 4, 8) X(12, 4, 8, 8) X(13, 4, 2, 16) X(14, 4, 4, 16) X(15, 4, 8, 16)
 
 }  // namespace
 
-int launch_stage_f64(int stage, int cls, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s);
-int launch_stage_f32(int stage, int cls, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s);
+int launch_stage_f64(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s);
+int launch_stage_f32(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s);
 
 }  // namespace rsl

@@ -1,10 +1,10 @@
 // binary32-storage instantiation of the fused Sod stage kernel.
-#include "sod_stage.h"
+#include "sod_split.h"
 
 namespace rsl {
 
-int launch_stage_f32(int stage, int cls, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s) {
-    return launch_stage_any<float>(stage, cls, d, cl, fb, wb, s);
+int launch_stage_f32(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s) {
+    return launch_stage_any<float>(stage, var, d, cl, fb, wb, s);
 }
 
 }  // namespace rsl

@@ -1,35 +1,72 @@
 // binary64 instantiation of the fused Sod stage kernel, and the dispatch.
-#include "sod_stage.h"
+#include "sod_split.h"
 
 namespace rsl {
 
-int launch_stage_f64(int stage, int cls, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s) {
-    return launch_stage_any<double>(stage, cls, d, cl, fb, wb, s);
+int launch_stage_f64(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s) {
+    return launch_stage_any<double>(stage, var, d, cl, fb, wb, s);
 }
 
-// Velocity-set classes of the stage kernel (see launch_cls).
+bool stage_variant_shape(int var, int* W, int* NV, int* TW, bool* split, int* WC) {
+    switch (var) {
+#define RSL_SHAPE(id, w, nv, tw) \
+    case id: *W = w; *NV = nv; *TW = tw; *split = false; *WC = 0; return true;
+        RSL_STAGE_VARIANTS(RSL_SHAPE)
+#undef RSL_SHAPE
+#define RSL_SHAPE(id, w, nv, wc) \
+    case id: *W = w; *NV = nv; *TW = kLanes; *split = true; *WC = wc; return true;
+        RSL_SPLIT_VARIANTS(RSL_SHAPE)
+#undef RSL_SHAPE
+        default: return false;
+    }
+}
+
+int stage_variant_capacity(int var) {
+    int W, NV, TW, WC;
+    bool split;
+    if (!stage_variant_shape(var, &W, &NV, &TW, &split, &WC)) return 0;
+    return split ? kMaxVelocities : W * (kLanes / TW) * NV;
+}
+
+int stage_variant_tile_cells(int var) {
+    int W, NV, TW, WC;
+    bool split;
+    return stage_variant_shape(var, &W, &NV, &TW, &split, &WC) ? TW - 1 : 0;
+}
+
+int stage_variant_count() {
+    int n = 0, W, NV, TW, WC;
+    bool split;
+    while (stage_variant_shape(n, &W, &NV, &TW, &split, &WC)) ++n;
+    return n;
+}
+
+// Default variant for a velocity set, and the batch class it belongs to.
+static const int kDefaultVariant[kClasses] = {13, 13, 14, 14, 14, 14, 14};
+
+// Largest V of each class (the last class takes every larger set).
+static const int kClassMaxV[kClasses] = {32, 64, 128, 256, 320, 384, kMaxVelocities};
+
 int stage_class_of(int V) {
-    if (V <= 4 * 8) return 0;
-    if (V <= 4 * 16) return 1;
-    if (V <= 8 * 16) return 2;
-    if (V <= 8 * 2 * 16) return 3;
-    if (V <= 8 * 2 * 20) return 4;
-    return V <= 8 * 2 * 24 ? 5 : -1;
+    for (int c = 0; c < kClasses; ++c)
+        if (V <= kClassMaxV[c]) return c;
+    return -1;
 }
 
-int stage_tile_cells(int cls) { return cls >= 3 ? 31 : 63; }
+int stage_default_variant(int cls) { return kDefaultVariant[cls]; }
 
 int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s) {
     const int cls = stage_class_of(d.V);
-    if (cls < 0) return set_error(RSL_EUNSUPPORTED, "Sod stage: more than 384 velocities");
-    if (d.dtype == RSL_F64) return launch_stage_f64(stage, cls, &d, nullptr, nullptr, nullptr, s);
-    return launch_stage_f32(stage, cls, &d, nullptr, nullptr, nullptr, s);
+    if (cls < 0) return set_error(RSL_EUNSUPPORTED, "Sod stage: velocity set too large");
+    const int var = kDefaultVariant[cls];
+    if (d.dtype == RSL_F64) return launch_stage_f64(stage, var, &d, nullptr, nullptr, nullptr, s);
+    return launch_stage_f32(stage, var, &d, nullptr, nullptr, nullptr, s);
 }
 
 int launch_sod_class_stage(const StageClass& cl, int dtype, int stage, char* fbase, char* wbase, hipStream_t s) {
     if (cl.nitems == 0) return RSL_OK;
-    if (dtype == RSL_F64) return launch_stage_f64(stage, cl.cls, nullptr, &cl, fbase, wbase, s);
-    return launch_stage_f32(stage, cl.cls, nullptr, &cl, fbase, wbase, s);
+    if (dtype == RSL_F64) return launch_stage_f64(stage, cl.var, nullptr, &cl, fbase, wbase, s);
+    return launch_stage_f32(stage, cl.var, nullptr, &cl, fbase, wbase, s);
 }
 
 }  // namespace rsl

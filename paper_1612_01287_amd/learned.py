@@ -52,10 +52,10 @@ class PairedEnsemble:
         for Q in ((self.q_lo, self.q_hi) if which is None else (which,)):
             self.batches[Q].step(nsteps, stream=stream)
 
-    def features(self):
+    def features(self, shift=None, scale=None):
         B = self.batches[self.q_lo]
-        feats = [rsl.features(self.quads[self.q_lo], B.problems[i], B.f(i), math.log(self.states[i][2]))
-                 for i in range(B.n)]
+        feats = [rsl.features(self.quads[self.q_lo], B.problems[i], B.f(i), math.log(self.states[i][2]),
+                              shift, scale) for i in range(B.n)]
         return torch.cat(feats, dim=0)
 
     def moments(self, Q):
@@ -78,47 +78,84 @@ def generate(n_runs, nz, t_snaps, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=128,
 
 
 class Correction:
-    """A trained network plus the feature range it was trained on (the guard)."""
+    """A trained network, the feature standardisation it expects and the range
+    of standardised features it was trained on (the guard)."""
 
-    def __init__(self, net, lo, hi):
+    def __init__(self, net, lo, hi, shift, scale):
         self.net, self.lo, self.hi = net, lo, hi
+        self.shift, self.scale = shift, scale
+
+    def features(self, ens):
+        """Standardised features of an ensemble's low-order states (one kernel per instance)."""
+        return ens.features(self.shift, self.scale)
 
     def apply(self, X, m_lo):
-        """Corrected (T^00, T^0z, T^zz) [N, 3] (fp64), or None when a feature
-        lies outside the training range (caller falls back to the high-order solve)."""
+        """Corrected (T^00, T^0z, T^zz) [N, 3] (fp64) from standardised features,
+        or None when a feature lies outside the training range (caller falls
+        back to the high-order solve)."""
         if rsl.guard(X, self.lo, self.hi):
             return None
         y = self.net.forward(X)
         return rsl.tmunu_correct(m_lo, y)
 
+    def outside(self, X):
+        """Indices of the features that leave the training range somewhere in X."""
+        out = ((X < self.lo) | (X > self.hi)).any(dim=0)
+        return [int(i) for i in torch.nonzero(out).flatten().tolist()]
 
-def train(X, T, epochs=20, batch=8192, lr=2e-3, seed=0, margin=0.05, init=None):
-    """Adam on shuffled minibatches with a cosine learning-rate decay; returns
-    the Correction (network + feature range for the guard) and the per-epoch
-    mean loss."""
+
+def train(X, T, epochs=20, batch=8192, lr=2e-3, seed=0, margin=0.05, init=None, min_scale=1e-4):
+    """Adam on shuffled minibatches with a cosine learning-rate decay.
+
+    Inputs are standardised per feature (mean, standard deviation floored at
+    min_scale; the features kernel applies the same map at inference) and the
+    targets are divided by their root mean square per output during training;
+    that factor is folded into the last layer afterwards, so the returned
+    network maps standardised features to the unscaled targets.  Returns the
+    Correction and the per-epoch mean loss in the scaled units."""
     g = torch.Generator(device="cpu").manual_seed(seed)
     n = X.shape[0]
+    shift = X.mean(dim=0).contiguous()
+    scale = X.std(dim=0).clamp_min(min_scale).contiguous()
+    Xs = ((X - shift) / scale).contiguous()
+    tsc = T.pow(2).mean(dim=0).sqrt().clamp_min(1e-30)
+    Ts = (T / tsc).contiguous()
     net = rsl.MLP(init if init is not None else _he_init(seed))
     hist = []
     step = 0
+    nb = (n + batch - 1) // batch
     for ep in range(epochs):
         perm = torch.randperm(n, generator=g).to(X.device)
         tot, cnt = 0.0, 0
         for s in range(0, n, batch):
             idx = perm[s:s + batch]
-            xb, tb = X[idx].contiguous(), T[idx].contiguous()
+            xb, tb = Xs[idx].contiguous(), Ts[idx].contiguous()
             y, h1, h2 = net.forward(xb, keep=True)
             net.backward(xb, h1, h2, y, tb)
-            lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / max(1, epochs * ((n + batch - 1) // batch))))
+            lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / max(1, epochs * nb)))
             net.adam(lr=lr_t)
             step += 1
             tot += float(((y - tb) ** 2).mean()) * xb.shape[0]
             cnt += xb.shape[0]
         hist.append(tot / cnt)
-    span = X.max(dim=0).values - X.min(dim=0).values
-    lo = (X.min(dim=0).values - margin * span - 1e-6).contiguous()
-    hi = (X.max(dim=0).values + margin * span + 1e-6).contiguous()
-    return Correction(net, lo, hi), hist
+    _fold_output_scale(net, tsc)
+    span = Xs.max(dim=0).values - Xs.min(dim=0).values
+    lo = (Xs.min(dim=0).values - margin * span - 1e-6).contiguous()
+    hi = (Xs.max(dim=0).values + margin * span + 1e-6).contiguous()
+    return Correction(net, lo, hi, shift, scale), hist
+
+
+def _fold_output_scale(net, tsc):
+    """W3 <- W3 diag(tsc), b3 <- b3 tsc on the fp32 master copy, then a fresh bf16 copy."""
+    o = 0
+    for name, shp in rsl.MLP_SHAPES:
+        k = int(np.prod(shp))
+        if name == "W3":
+            net.params[o:o + k].view(shp).mul_(tsc.to(net.params.dtype))
+        elif name == "b3":
+            net.params[o:o + k].mul_(tsc.to(net.params.dtype))
+        o += k
+    net.refresh()
 
 
 def _he_init(seed):
@@ -145,7 +182,7 @@ def evaluate(corr, n_inst, nz, t_end, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ens.advance(nsteps, which=q_lo, stream=stream)
-    X = ens.features()
+    X = corr.features(ens)
     m_lo = ens.moments(q_lo)
     Tc = corr.apply(X, m_lo)
     torch.cuda.synchronize()
@@ -161,5 +198,7 @@ def evaluate(corr, n_inst, nz, t_end, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=
         return float(torch.linalg.norm(a - Thi) / torch.linalg.norm(Thi))
     out = {"err_lo": rel(Tlo), "t_learned_s": t_learned, "t_high_order_s": t_hi,
            "fallback": Tc is None, "cells": int(Thi.shape[0])}
+    if Tc is None:
+        out["features_outside"] = corr.outside(X)
     out["err_corrected"] = rel(Tc) if Tc is not None else None
     return out

@@ -210,6 +210,24 @@ _sig("rsl_batch_graph_step", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_set_path", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("rsl_batch_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("rsl_batch_status", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)])
+_ip = ctypes.POINTER(ctypes.c_int)
+_sig("rsl_stage_variant", ctypes.c_int, [ctypes.c_int, _ip, _ip, _ip, _ip, _ip])
+_sig("rsl_batch_variant", ctypes.c_int, [_vp, ctypes.c_int, _ip, _ip])
+_sig("rsl_batch_set_variant", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int])
+_sig("rsl_batch_autotune", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _ip])
+
+N_CLASSES = 7
+
+
+def stage_variants():
+    """[(waves, velocities per lane, lanes per velocity, largest V, cell-kernel
+    waves (0: fused form))] of every stage-kernel variant, by id."""
+    out = []
+    while True:
+        r = [ctypes.c_int() for _ in range(5)]
+        if _lib.rsl_stage_variant(len(out), *[ctypes.byref(x) for x in r]) != 0:
+            return out
+        out.append(tuple(x.value for x in r))
 
 
 class Batch:
@@ -250,6 +268,23 @@ class Batch:
     def set_path(self, path):
         """Bjorken batches: -1 automatic, 0 vector units, 1 matrix cores."""
         check(_lib.rsl_batch_set_path(self._h, int(path)))
+
+    def variant(self, cls):
+        """(variant id or -1 for an empty class, largest V of the class)."""
+        v, mv = ctypes.c_int(), ctypes.c_int()
+        check(_lib.rsl_batch_variant(self._h, int(cls), ctypes.byref(v), ctypes.byref(mv)))
+        return v.value, mv.value
+
+    def set_variant(self, cls, var):
+        check(_lib.rsl_batch_set_variant(self._h, int(cls), int(var)))
+
+    def autotune(self, reps=5, stream=None):
+        """Times every fitting kernel variant per class and keeps the fastest;
+        returns the chosen ids per class (-1: empty class)."""
+        f, w = self._ptrs()
+        out = (ctypes.c_int * N_CLASSES)()
+        check(_lib.rsl_batch_autotune(self._h, f, w, int(reps), _stream(stream), out))
+        return list(out)
 
     def stage(self, s, stream=None):
         f, w = self._ptrs()
@@ -292,7 +327,7 @@ class Batch:
 
 
 _u16p = ctypes.c_void_p
-_sig("rsl_mlp_features", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, ctypes.c_double, _vp, _vp])
+_sig("rsl_mlp_features", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, ctypes.c_double, _vp, _vp, _vp, _vp])
 _sig("rsl_mlp_to_bf16", ctypes.c_int, [_vp, _vp, _vp])
 _sig("rsl_mlp_forward", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp])
 _sig("rsl_mlp_backward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp])
@@ -364,11 +399,12 @@ class MLP:
         return np.concatenate([np.asarray(P[name], dtype=np.float64).ravel() for name, _ in MLP_SHAPES])
 
 
-def features(quad, problem, f_buf, log_tau, stream=None):
-    """[nz, 81] fp32 features of one Sod instance's state buffer."""
+def features(quad, problem, f_buf, log_tau, shift=None, scale=None, stream=None):
+    """[nz, 81] fp32 features of one Sod instance's state buffer, standardised
+    as (x - shift) / scale when shift and scale ([81] fp32 device tensors) are given."""
     out = torch.empty((problem.nz, 81), dtype=torch.float32, device=f_buf.device)
-    check(_lib.rsl_mlp_features(quad.handle, ctypes.byref(problem), _p(f_buf), float(log_tau), _p(out),
-                                _stream(stream)))
+    check(_lib.rsl_mlp_features(quad.handle, ctypes.byref(problem), _p(f_buf), float(log_tau), _p(shift), _p(scale),
+                                _p(out), _stream(stream)))
     return out
 
 

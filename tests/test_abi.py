@@ -80,3 +80,20 @@ def test_tables_match_oracle(rsl, QL, Q):
     assert np.max(np.abs(KL - vs.KL)) < 1e-14 * np.max(np.abs(vs.KL))
     KP = q.table(rsl.RSL_TAB_KP).reshape(Q, Q)
     assert np.max(np.abs(KP - vs.KP)) < 1e-13 * np.max(np.abs(vs.KP))
+
+
+def test_stage_variants_cover_every_class(rsl):
+    vs = rsl.stage_variants()
+    assert len(vs) >= 7
+    fused = []
+    for W, NV, TW, max_v, wc in vs:
+        assert TW in (32, 64) and 1 <= W <= 16 and NV >= 1
+        if wc:
+            assert TW == 64 and max_v >= 8 * 1024 and wc in (4, 8, 16)   # any Q_xi <= 1024 at Q_L <= 8
+        else:
+            assert max_v == W * (64 // TW) * NV
+            fused.append(max_v)
+    for bound in (32, 64, 128, 256, 320, 384):
+        assert any(c >= bound for c in fused)
+    assert max(fused) == 384
+    assert any(v[4] for v in vs)

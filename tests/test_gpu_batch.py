@@ -77,6 +77,91 @@ def test_sod_batch_stage_by_stage(rsl):
         assert torch.equal(A.f(i), B.f(i))
 
 
+def _fits(rsl, cap_needed):
+    return [v for v, sh in enumerate(rsl.stage_variants()) if sh[3] >= cap_needed]
+
+
+def _ragged_all_classes(rsl, dtype):
+    """Instances in all seven velocity classes (V = 24, 48, 120, 192, 300, 384, 450)."""
+    quads, probs, dts = [], [], []
+    for i, (Q, nz) in enumerate([(8, 200), (16, 77), (40, 130), (64, 64), (100, 95), (128, 33), (8, 5),
+                                 (150, 70)]):
+        quads.append(rsl.Quadrature(3, Q, min(Q - 1, 4)))
+        TR = 1.0 / (1.2 + 0.2 * i)
+        probs.append(rsl.make_problem(nz=nz, dtype=dtype, bc="eq" if i % 2 else "outflow", tau_r=0.02 + 0.01 * i,
+                                      nL=1.0, TL=1.0, nR=TR ** 3, TR=TR))
+        dts.append(0.4 / nz)
+    return quads, probs, dts
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_every_stage_variant_matches_default(rsl, dtype, tol):
+    """Variants change only the order of the per-cell moment sums."""
+    quads, probs, dts = _ragged_all_classes(rsl, dtype)
+    ref = rsl.Batch(quads, probs, dts)
+    ref.init()
+    ref.step(2)
+    torch.cuda.synchronize()
+    want = [ref.f(i).double().cpu().numpy() for i in range(ref.n)]
+    B = rsl.Batch(quads, probs, dts)
+    tried = 0
+    for cls in range(rsl.N_CLASSES):
+        var0, maxv = B.variant(cls)
+        assert var0 >= 0 and maxv > 0
+        for v in _fits(rsl, maxv):
+            B.set_variant(cls, v)
+            assert B.variant(cls)[0] == v
+            B.init()
+            B.step(2)
+            torch.cuda.synchronize()
+            for i in range(B.n):
+                got = B.f(i).double().cpu().numpy()
+                err = np.max(np.abs(got - want[i])) / np.max(np.abs(want[i]))
+                assert err < tol, (cls, v, i, err)
+            tried += 1
+        B.set_variant(cls, -1)
+        assert B.variant(cls)[0] == var0
+    assert tried >= 20
+    rc, bad = B.status()
+    assert rc == 0 and bad == -1
+
+
+def test_set_variant_rejects_small_variants(rsl):
+    quads, probs, dts = _ragged_all_classes(rsl, "f64")
+    B = rsl.Batch(quads, probs, dts)
+    caps = [sh[3] for sh in rsl.stage_variants()]
+    small = int(np.argmin(caps))
+    with pytest.raises(RuntimeError):
+        B.set_variant(5, small)        # class of V = 384
+    with pytest.raises(RuntimeError):
+        B.set_variant(0, len(caps))    # no such variant
+
+
+def test_autotune_keeps_state_and_results(rsl):
+    quads, probs, dts = _ragged_all_classes(rsl, "f64")
+    B = rsl.Batch(quads, probs, dts)
+    B.init()
+    B.step(1)
+    torch.cuda.synchronize()
+    before = [B.f(i).clone() for i in range(B.n)]
+    chosen = B.autotune(reps=2)
+    torch.cuda.synchronize()
+    caps = [sh[3] for sh in rsl.stage_variants()]
+    for cls, v in enumerate(chosen):
+        var, maxv = B.variant(cls)
+        assert v == var and caps[v] >= maxv
+    for i in range(B.n):
+        assert torch.equal(before[i], B.f(i))
+    A = rsl.Batch(quads, probs, dts)
+    A.init()
+    A.step(3)
+    B.step(2)
+    torch.cuda.synchronize()
+    for i in range(B.n):
+        a, b = A.f(i).cpu().numpy(), B.f(i).cpu().numpy()
+        assert np.max(np.abs(a - b)) / np.max(np.abs(a)) < 1e-12
+
+
 def test_bjorken_batch_equals_single(rsl):
     rng = np.random.default_rng(3)
     quads, probs, dts = [], [], []

@@ -45,6 +45,22 @@ def test_features_match_oracle(rsl):
         assert np.max(np.abs(got - ref) / (np.abs(ref) + 1e-3)) < 2e-6
 
 
+def test_standardised_features(rsl):
+    """(x - shift) / scale in fp32, as the training data are prepared."""
+    quad = rsl.Quadrature(3, 16, 4)
+    p = rsl.make_problem(nz=300, dtype="f64", tau_r=0.05)
+    inst = rsl.Instance(quad, p)
+    inst.init()
+    inst.step(0.5 / 300, 20)
+    raw = rsl.features(quad, p, inst.f_buf, np.log(0.05))
+    shift = raw.mean(dim=0).contiguous()
+    scale = raw.std(dim=0).clamp_min(1e-4).contiguous()
+    got = rsl.features(quad, p, inst.f_buf, np.log(0.05), shift, scale)
+    assert torch.equal(got, (raw - shift) / scale)
+    with pytest.raises(RuntimeError):
+        rsl.features(quad, p, inst.f_buf, np.log(0.05), shift, None)
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 1000])
 def test_forward_backward_match_oracle(rsl, n):
     rng = np.random.default_rng(n)

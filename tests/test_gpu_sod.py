@@ -149,6 +149,16 @@ def test_velocity_classes_above_256(rsl, QL, Q):
     assert _rel(inst.f().cpu().numpy(), S.run(S.init(), dt, 2)) < TOL["f64"]
 
 
+@pytest.mark.parametrize("QL,Q,nz,bc", [(3, 200, 150, "eq"), (4, 256, 64, "outflow"), (3, 129, 70, "eq")])
+def test_velocity_sets_above_384(rsl, QL, Q, nz, bc):
+    """Large velocity sets (V > 384) run in the two-kernel stage form."""
+    quad, inst, vs, S = _pair(rsl, QL, Q, 4, nz, bc=bc, tau_mode="etas", tau_aw0=0.3854 * 0.1)
+    inst.init()
+    dt = 0.5 / nz
+    inst.step(dt, 2)
+    assert _rel(inst.f().cpu().numpy(), S.run(S.init(), dt, 2)) < TOL["f64"]
+
+
 def test_c2_full_size(rsl):
     """C2 size: N_z = 4096, R-SLB(4;100), Q_L = 3, eta/s = 0.01, 2 steps."""
     quad, inst, vs, S = _pair(rsl, 3, 100, 4, 4096, tau_mode="etas", tau_aw0=0.3854 * 0.01)
@@ -158,7 +168,8 @@ def test_c2_full_size(rsl):
     assert _rel(inst.f().cpu().numpy(), S.run(S.init(), dt, 2)) < TOL["f64"]
 
 
-@pytest.mark.parametrize("QL,Q,NOm,nz", [(3, 8, 3, 130), (3, 16, 4, 257), (3, 64, 4, 100), (3, 128, 4, 90)])
+@pytest.mark.parametrize("QL,Q,NOm,nz", [(3, 8, 3, 130), (3, 16, 4, 257), (3, 64, 4, 100), (3, 128, 4, 90),
+                                        (3, 160, 4, 70)])
 def test_fp32_storage(rsl, QL, Q, NOm, nz):
     """f in binary32, per-cell work in binary64: one-step parity at 1e-5 along
     a 20-step trajectory, end state within the oracle's binary32 envelope."""
