@@ -162,10 +162,14 @@ const char* rsl_last_error(void);
 
 /* ---------------------------------------------------------------- batches
  * Many instances of one problem kind and one dtype, of uneven nz, velocity
- * set and relaxation law, advanced together.  Sod batches run one launch per
- * RK stage for all instances (work items = (instance, 63-cell tile), ordered
- * per XCD, costliest first); Bjorken batches run one launch per call (one
- * workgroup per instance, all steps inside).  Each instance has its own time
+ * set and relaxation law, advanced together.  Sod batches sort their
+ * instances into velocity classes (see the stage-kernel variants below); per
+ * RK stage each class runs one launch (fused form) or two (two-kernel form)
+ * over all its instances (work items = (instance, tile), ordered per XCD,
+ * costliest first), each class on a stream of its own forked from and joined
+ * back into the caller's stream once per call.  Bjorken batches run one
+ * launch per call (one workgroup per instance or per group of 16 instances
+ * with one velocity set, all steps inside).  Each instance has its own time
  * step dt[i].  The batch copies the problem structs and keeps pointers to the
  * quads, which must outlive it.  Device memory of the batch (descriptor and
  * work-item tables) is allocated at creation; stepping allocates nothing and

@@ -205,11 +205,38 @@ int batch_stage_all(rsl_batch* b, int stage, char* f, char* w, hipStream_t s) {
     return rc;
 }
 
+// nsteps RK3 steps of every Sod instance.  Velocity classes hold disjoint
+// instances, so each class runs all its stages on a stream of its own (forked
+// from and joined back into the caller's stream once per call): no
+// cross-stream wait between stages, and one class's per-cell kernel overlaps
+// another class's stream kernel.
+int batch_sod_steps(rsl_batch* b, char* f, char* w, int nsteps, hipStream_t s) {
+    int used[kClasses], nu = 0;
+    for (int c = 0; c < kClasses; ++c)
+        if (b->launch.cl[c].nitems) used[nu++] = c;
+    int rc = RSL_OK;
+    if (nu > 1) {
+        if ((rc = batch_streams(b))) return rc;
+        if ((rc = hip_check(hipEventRecord(b->ev_fork, s), "hipEventRecord"))) return rc;
+        for (int k = 1; k < nu && rc == RSL_OK; ++k)
+            rc = hip_check(hipStreamWaitEvent(b->aux[k], b->ev_fork, 0), "hipStreamWaitEvent");
+    }
+    for (int k = 0; k < nu && rc == RSL_OK; ++k)
+        for (int it = 0; it < nsteps && rc == RSL_OK; ++it)
+            for (int st = 1; st <= 3 && rc == RSL_OK; ++st)
+                rc = launch_sod_class_stage(b->launch.cl[used[k]], b->dtype, st, f, w, k ? b->aux[k] : s);
+    if (nu > 1)
+        for (int k = 1; k < nu && rc == RSL_OK; ++k) {
+            rc = hip_check(hipEventRecord(b->ev_join[k], b->aux[k]), "hipEventRecord");
+            if (rc == RSL_OK) rc = hip_check(hipStreamWaitEvent(s, b->ev_join[k], 0), "hipStreamWaitEvent");
+        }
+    return rc;
+}
+
 int batch_steps(rsl_batch* b, char* f, char* w, int nsteps, hipStream_t s) {
     int rc = RSL_OK;
     if (b->kind == RSL_SOD) {
-        for (int it = 0; it < nsteps && rc == RSL_OK; ++it)
-            for (int st = 1; st <= 3 && rc == RSL_OK; ++st) rc = batch_stage_all(b, st, f, w, s);
+        if (nsteps > 0) rc = batch_sod_steps(b, f, w, nsteps, s);
     } else if (nsteps > 0) {
         const bool mfma = b->use_mfma && b->bj_path != 0;
         if (mfma)

@@ -145,7 +145,7 @@ void series_tables(std::vector<double>& ser, std::vector<double>& thr) {
         cser.assign(2 * NM * NT, 0.0);
         for (int kk = 0; kk < 2; ++kk)
             for (int m = 0; m < NM; ++m)
-                for (int i = 0; i < NT; ++i) cser[(kk * NM + m) * NT + i] = (double)A[(kk * NM + m) * NA + i];
+                for (int i = 0; i < NT; ++i) cser[(size_t)i * 2 * NM + kk * NM + m] = (double)A[(kk * NM + m) * NA + i];
         auto ok = [&](int nt, ld x) {
             for (int s = 0; s < 2 * NM; ++s) {
                 ld head = 0.0L, tail = 0.0L, p = 1.0L;

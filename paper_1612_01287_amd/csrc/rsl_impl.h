@@ -30,7 +30,7 @@ struct QuadDev {
     const double* pk;    // [QL]     p_k = T0 * pbar_k
     const double* L1;    // [QL]     L_1^(2)(pbar_k) = 3 - pbar_k
     const double* Pm;    // [(NOm+1)*Q]  P_m(xi_j), row m
-    const double* ser;   // [2][kMaxNOm+1][kSeriesTerms]  Maclaurin coefficients of K_{3,m}, K_{4,m}
+    const double* ser;   // [kSeriesTerms][2][kMaxNOm+1]  Maclaurin coefficients of K_{3,m}, K_{4,m}
     const double* thr;   // [kSeriesTerms]  beta^2 below which i terms suffice
     const double* KL;    // [QL*QL]
     const double* KP;    // [Q*Q]

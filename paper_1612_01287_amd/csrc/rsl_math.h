@@ -59,24 +59,51 @@ __device__ __forceinline__ CellState landau(double N0, double Nz, double T00, do
     return c;
 }
 
-// K_{3,m}, K_{4,m} for m = 0..nom (nom <= kMaxNOm).
+// Number of Maclaurin terms that carry K_{3,m}, K_{4,m} to full precision for
+// every beta^2 <= x (thr is ascending).
+__device__ __forceinline__ int series_terms(double x, const double* __restrict__ thr) {
+    int nt = 1;
+    while (nt < kSeriesTerms && x > thr[nt]) ++nt;
+    return nt;
+}
+
+// The same count for a wave-uniform x, through scalar loads.
+__device__ __forceinline__ int series_terms_uniform(double x, const double* __restrict__ thr) {
+    int nt = 1;
+    while (nt < kSeriesTerms && x > ((const __attribute__((address_space(4))) double*)thr)[nt]) ++nt;
+    return nt;
+}
+
+// Largest x over the 64 lanes of a wave (all lanes active), as a wave-uniform value.
+__device__ __forceinline__ double wave_max_uniform(double x) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) x = fmax(x, __shfl_xor(x, o));
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+// K_{3,m}, K_{4,m} for m = 0..nom (nom <= kMaxNOm); nt terms of the series
+// when |beta| < beta_s (nt from series_terms for beta^2 or anything larger:
+// extra terms only add values below the last bit).  The coefficient loop is
+// uniform when nt is, so the table comes through scalar loads.
 __device__ __forceinline__ void kint(double beta, int nom, double beta_s, const double* __restrict__ ser,
-                                     const double* __restrict__ thr, double* K3, double* K4) {
+                                     int nt, double* K3, double* K4) {
     const double ab = fabs(beta);
     if (ab < beta_s) {
         const double x = beta * beta;
-        int nt = 1;
-        while (nt < kSeriesTerms && x > thr[nt]) ++nt;
         double s3[kMaxNOm + 1], s4[kMaxNOm + 1];
 #pragma unroll
         for (int m = 0; m <= kMaxNOm; ++m) s3[m] = s4[m] = 0.0;
         double p = 1.0;
         for (int i = 0; i < nt; ++i) {
+            const __attribute__((address_space(4))) double* a =
+                (const __attribute__((address_space(4))) double*)ser + (size_t)i * 2 * (kMaxNOm + 1);
 #pragma unroll
             for (int m = 0; m <= kMaxNOm; ++m) {
                 if (m <= nom) {
-                    s3[m] = fma(ser[m * kSeriesTerms + i], p, s3[m]);
-                    s4[m] = fma(ser[(kMaxNOm + 1 + m) * kSeriesTerms + i], p, s4[m]);
+                    s3[m] = fma(a[m], p, s3[m]);
+                    s4[m] = fma(a[kMaxNOm + 1 + m], p, s4[m]);
                 }
             }
             p *= x;
@@ -117,11 +144,12 @@ __device__ __forceinline__ void kint(double beta, int nom, double beta_s, const 
 //   f^eq_jk = w_j w_k sum_m P_m(xi_j) (c0[m] + L_1(pbar_k) c1[m]),
 //   c0[m] = h_m K_{3,m},  c1[m] = h_m (K_{3,m} - (theta/gamma) K_{4,m}),
 //   h_m = n (2m+1) / (8 gamma^3).
+// nt: series terms (see kint).
 __device__ __forceinline__ void feq_coef(double n, double T, double beta, double gamma, double T0,
-                                         int nom, double beta_s, const double* ser, const double* thr,
+                                         int nom, double beta_s, const double* ser, int nt,
                                          double* c0, double* c1) {
     double K3[kMaxNOm + 1], K4[kMaxNOm + 1];
-    kint(beta, nom, beta_s, ser, thr, K3, K4);
+    kint(beta, nom, beta_s, ser, nt, K3, K4);
     const double h0 = n / (8.0 * gamma * gamma * gamma);
     const double tg = T / (T0 * gamma);
 #pragma unroll

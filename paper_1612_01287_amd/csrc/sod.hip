@@ -33,7 +33,7 @@ __global__ void boundary_state_kernel(InstDesc d, double nL, double TL, double n
     double c0[kMaxNOm + 1], c1[kMaxNOm + 1];
     for (int side = 0; side < 2; ++side) {
         const double n = side ? nR : nL, T = side ? TR : TL;
-        feq_coef(n, T, 0.0, 1.0, d.T0, d.NOm, d.beta_series, d.tab.ser, d.tab.thr, c0, c1);
+        feq_coef(n, T, 0.0, 1.0, d.T0, d.NOm, d.beta_series, d.tab.ser, 1, c0, c1);
         double g = 0.0;
         for (int m = 0; m <= d.NOm; ++m) g += d.tab.Pm[m * d.Q + j] * (c0[m] + d.tab.L1[k] * c1[m]);
         (side ? outR : outL)[v] = d.tab.wxw[v] * g;

@@ -66,7 +66,9 @@ __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, double* r
     red[(w * 5 + 3) * kLanes + lane] = m3;
     red[(w * 5 + 4) * kLanes + lane] = m4;
     __syncthreads();
-    if (w != 0 || !live) return;
+    if (w != 0) return;
+    // wave 0, all 64 lanes: per-cell coefficients (lanes without a cell carry
+    // a rest state so that the series term count stays wave-uniform)
     double M[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
@@ -76,10 +78,11 @@ __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, double* r
         M[q] = sum;
     }
     CellState cs = landau(M[0], M[1], M[2], M[3], M[4]);
-    if (!cs.ok) {
-        atomicOr(d.status, 1u);
+    if (live && !cs.ok) atomicOr(d.status, 1u);
+    if (!live || !cs.ok) {
         cs.n = 1.0; cs.T = 1.0; cs.beta = 0.0; cs.gamma = 1.0;
     }
+    const int nt = series_terms_uniform(wave_max_uniform(cs.beta * cs.beta), d.tab.thr);
     double tau = d.tau_r;
     if (d.tau_mode == RSL_TAU_ETAS) {
         const double lam = cs.n / (cs.T * cs.T * cs.T);
@@ -87,7 +90,8 @@ __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, double* r
     }
     const double it = 1.0 / tau;
     double c0[kMaxNOm + 1], c1[kMaxNOm + 1];
-    feq_coef(cs.n, cs.T, cs.beta, cs.gamma, d.T0, d.NOm, d.beta_series, d.tab.ser, d.tab.thr, c0, c1);
+    feq_coef(cs.n, cs.T, cs.beta, cs.gamma, d.T0, d.NOm, d.beta_series, d.tab.ser, nt, c0, c1);
+    if (!live) return;
     double* out = d.cell + c;
     out[0] = cs.gamma * it;
     out[pitch] = cs.gamma * cs.beta * it;

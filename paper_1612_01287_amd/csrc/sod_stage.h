@@ -260,7 +260,8 @@ __device__ __forceinline__ void stage_tile(const InstDesc& d, int tile, char* ld
         }
         const double it = 1.0 / tau;
         double c0[kMaxNOm + 1], c1[kMaxNOm + 1];
-        feq_coef(cs.n, cs.T, cs.beta, cs.gamma, d.T0, d.NOm, d.beta_series, d.tab.ser, d.tab.thr, c0, c1);
+        const int nt = series_terms(cs.beta * cs.beta, d.tab.thr);
+        feq_coef(cs.n, cs.T, cs.beta, cs.gamma, d.T0, d.NOm, d.beta_series, d.tab.ser, nt, c0, c1);
         double* pp = par + cl * kPar;
         pp[0] = cs.gamma * it;
         pp[1] = cs.gamma * cs.beta * it;

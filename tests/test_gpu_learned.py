@@ -1,7 +1,8 @@
 """End-to-end learned correction on the GPU: paired low/high-order Sod data from
-the solver, training with the library's own forward/backward/Adam kernels, and
-the gain over the uncorrected low-order set on unseen instances (scaled-down
-version of the 8192-cell, 512-instance evaluation)."""
+the solver (R-SLB(4;8) vs R-SLB(4;64), Q_L = 3), training with the library's
+own forward/backward/Adam kernels on 655 360 samples, and the gain over the
+uncorrected low-order set on unseen instances (scaled-down version of the
+8192-cell, 512-instance evaluation against R-SLB(4;128))."""
 import pytest
 import torch
 
@@ -10,16 +11,17 @@ pytestmark = pytest.mark.gpu
 
 def test_learned_correction_gain():
     from paper_1612_01287_amd import learned
-    X, T = learned.generate(n_runs=16, nz=512, t_snaps=(0.1, 0.175, 0.25), seed=5, q_lo=8, q_hi=64)
-    assert X.shape == (16 * 512 * 3, 81) and torch.isfinite(X).all() and torch.isfinite(T).all()
-    corr, hist = learned.train(X, T, epochs=40, batch=2048, lr=3e-3, seed=1, margin=0.25)
-    assert hist[-1] < 0.3 * hist[0]
-    # unseen instances drawn from inside the training distribution
-    res = learned.evaluate(corr, n_inst=4, nz=512, t_end=0.25, seed=6, tau_range=(0.03, 0.3), q_lo=8, q_hi=64)
-    print(res)
-    if res["fallback"]:
-        pytest.skip("evaluation features left the training range: fallback to the high-order solve (%s)" % res)
-    assert res["err_corrected"] < 0.7 * res["err_lo"], res
+    X, T = learned.generate(n_runs=256, nz=512, t_snaps=(0.05, 0.1, 0.15, 0.2, 0.25), seed=5, q_lo=8, q_hi=64)
+    assert X.shape == (256 * 512 * 5, 81) and torch.isfinite(X).all() and torch.isfinite(T).all()
+    corr, hist = learned.train(X, T, epochs=60, batch=4096, lr=2e-3, seed=1, margin=0.25)
+    assert hist[-1] < 0.1 * hist[0]
+    # unseen instances from the training distribution (tau_r log-uniform in [0.01, 1])
+    for seed, t_end in ((7, 0.25), (8, 0.15)):
+        res = learned.evaluate(corr, n_inst=16, nz=512, t_end=t_end, seed=seed, q_lo=8, q_hi=64)
+        print(res)
+        if res["fallback"]:
+            pytest.skip("evaluation features left the training range: fallback to the high-order solve (%s)" % res)
+        assert res["err_corrected"] < 0.5 * res["err_lo"], res
 
 
 def test_guard_triggers_fallback():
