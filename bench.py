@@ -9,7 +9,20 @@ one TVD-RK3 step (three fused stage kernels) of all sixteen instances.
 Metric: distribution updates per second, one update = one (cell, velocity,
 RK stage).
 
-Prints one JSON line (see the repository's measurement contract).
+Prints one JSON line (see the repository's measurement contract).  Its "aux"
+object carries three further measurements on seeded synthetic inputs:
+  bjorken  4096 Bjorken runs (T0 log-uniform in [0.5, 2] GeV, eta/s
+           log-uniform in [0.01, 10], Q_xi uniform in {20..200}, Q_L = 3,
+           ideal gas), a 1000-step window at dtau = 1e-3 in one launch; the
+           K^P F product on the matrix cores against the FP64 MFMA peak;
+  ensemble 1024 uneven Sod instances (N_z log-uniform in [256, 16384],
+           Q_xi in {8, 16, 32, 64}, T_L/T_R uniform in [1.1, 3], tau_r
+           log-uniform in [1e-4, 1], dt = min(0.5/N_z, tau_r/2)), f in
+           binary32, graph replays; 1.4 GB per field, so HBM-bound;
+  learned  the learned T^{mu nu} correction, scaled down (64 paired training
+           runs and 64 evaluation instances at N_z = 2048 instead of 8192):
+           R-SLB(4;8) + features + network against the plain R-SLB(4;128)
+           solve, wall time and relative T^{mu nu} error at t = 0.25.
 """
 import argparse
 import hashlib
@@ -28,6 +41,8 @@ QL = 3
 NOM = 4
 BYTES_PER_CELL_VEL_STEP = {"f64": 64, "f32": 32}   # f_n read 3x, stage fields read 2x, written 3x
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+HBARC = 0.1973269804      # GeV fm
 CHUNK = 10          # RK3 steps per captured HIP graph
 # HBM bytes per stage launch group read from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # counters (scaled by a plain copy kernel's readings); valid only for the
@@ -46,6 +61,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default stage-kernel variants")
     ap.add_argument("--variants", default=None,
                     help="comma-separated stage-kernel variant per velocity class (-1: empty); skips the autotuner")
+    ap.add_argument("--aux", default="all", choices=("none", "all"),
+                    help="also measure the Bjorken batch, the uneven Sod ensemble and the learned correction")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy five times (the reference kernel for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -122,6 +139,96 @@ def kernel_roofline(torch, B, dtype, updates_per_step, variants, chunk, stream, 
                        "stages)" % (3 * chunk * reps), avg_launch_us=round(ms * 1e3, 2),
                 bytes_per_launch=bytes_per_launch, variants=variants, kernel_forms=kernel_forms(variants),
                 kernel_source_hash=kernel_source_hash())
+
+
+def _events(torch, stream, fn, reps=1):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3
+
+
+def bjorken_leg(torch, rsl, stream, n=4096, window=1000, seed=3):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    quads, qs, probs = {}, [], []
+    flop_stage = 0.0
+    for _ in range(n):
+        Q = int(rng.integers(20, 201))
+        T0 = float(np.exp(rng.uniform(np.log(0.5), np.log(2.0))))
+        es = float(np.exp(rng.uniform(np.log(0.01), np.log(10.0))))
+        if Q not in quads:
+            quads[Q] = rsl.Quadrature(QL, Q, 4)
+        qs.append(quads[Q])
+        probs.append(rsl.make_problem(kind="bjorken", gas="ideal", tau_mode="etas",
+                                      tau_aw0=5 * HBARC * es / (0.25 * T0)))
+        flop_stage += 2.0 * Q * Q * QL
+    B = rsl.Batch(qs, probs, [1e-3] * n)
+    B.init(stream=stream)
+    B.step(10, stream=stream)
+    sec = _events(torch, stream, lambda: B.step(window, stream=stream))
+    rc, bad = B.status(stream)
+    assert rc == 0, "non-finite Bjorken instance %d" % bad
+    updates = 3.0 * window * sum(q.V for q in qs)
+    tflops = 3.0 * window * flop_stage / sec / 1e12
+    return {"workload": "4096 Bjorken runs, Q_xi uniform in {20..200}, Q_L = 3, 1000 steps of dtau = 1e-3, f64",
+            "value": updates / sec, "unit": "updates/s", "seconds": sec,
+            "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / FP64_MFMA_PEAK_TFLOPS, 4),
+                         "kernel": "bj_mfma_kernel (K^P F, 2 Q_xi^2 Q_L flop per instance and stage)"}}
+
+
+def ensemble_leg(torch, rsl, stream, n=1024, steps=20, chunk=10, seed=4):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    quads = {Q: rsl.Quadrature(QL, Q, min(Q - 1, 4)) for Q in (8, 16, 32, 64)}
+    qs, probs, dts = [], [], []
+    for _ in range(n):
+        nz = int(round(np.exp(rng.uniform(np.log(256), np.log(16384)))))
+        Q = int(rng.choice((8, 16, 32, 64)))
+        TR = 1.0 / rng.uniform(1.1, 3.0)
+        tau = float(np.exp(rng.uniform(np.log(1e-4), np.log(1.0))))
+        qs.append(quads[Q])
+        probs.append(rsl.make_problem(nz=nz, dtype="f32", bc="outflow", tau_r=tau, nL=1.0, TL=1.0,
+                                      nR=TR ** 3, TR=TR))
+        dts.append(min(0.5 / nz, 0.5 * tau))
+    B = rsl.Batch(qs, probs, dts)
+    B.init(stream=stream)
+    B.autotune(reps=3, stream=stream)
+    B.graph_step(chunk, stream=stream)
+    sec = _events(torch, stream, lambda: B.graph_step(chunk, stream=stream), reps=steps // chunk)
+    rc, bad = B.status(stream)
+    assert rc == 0, "non-finite ensemble instance %d" % bad
+    cellvel = sum(p.nz * q.V for p, q in zip(probs, qs))
+    updates = 3.0 * cellvel * steps
+    gbs = 32.0 * cellvel * steps / sec / 1e9
+    return {"workload": "1024 uneven Sod instances, N_z log-uniform in [256, 16384], Q_xi in {8,16,32,64}, f32",
+            "value": updates / sec, "unit": "updates/s", "ms_per_step": sec / steps * 1e3,
+            "f_bytes_per_field": 4 * cellvel,
+            "variants": [B.variant(c)[0] for c in range(rsl.N_CLASSES)],
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "kernel": "Sod stage kernels of all classes, 32 B per cell-velocity and step"}}
+
+
+def learned_leg(torch, stream):
+    from paper_1612_01287_amd import learned
+    t0 = time.perf_counter()
+    X, T = learned.generate(n_runs=64, nz=2048, t_snaps=(0.05, 0.1, 0.15, 0.2, 0.25), seed=5, q_lo=8, q_hi=128)
+    corr, hist = learned.train(X, T, epochs=30, batch=4096, lr=2e-3, seed=1, margin=0.25)
+    torch.cuda.synchronize()
+    prep = time.perf_counter() - t0
+    res = learned.evaluate(corr, n_inst=64, nz=2048, t_end=0.25, seed=6, q_lo=8, q_hi=128)
+    out = {"workload": "learned T^{mu nu} correction: R-SLB(4;8) + network vs R-SLB(4;128), 64 instances, "
+                       "N_z = 2048, t = 0.25 (scaled from 512 x 8192)",
+           "samples": int(X.shape[0]), "train_and_data_s": prep, "final_loss_scaled": hist[-1]}
+    out.update(res)
+    if res["err_corrected"] is not None:
+        out["speedup_vs_plain"] = res["t_high_order_s"] / res["t_learned_s"]
+    return out
 
 
 def cpu_baseline(dtype, budget_s=15.0):
@@ -216,6 +323,11 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roof,
     }
+    if a.aux == "all":
+        with torch.cuda.stream(stream):
+            out["aux"] = {"bjorken": bjorken_leg(torch, rsl, stream),
+                          "ensemble": ensemble_leg(torch, rsl, stream),
+                          "learned": learned_leg(torch, stream)}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.dtype)
     print(json.dumps(out))

@@ -176,7 +176,9 @@ const char* rsl_last_error(void);
  * may be captured into a HIP graph.
  * Buffers: one f buffer and one work buffer for the whole batch
  * (rsl_batch_sizes); instance i's f starts rsl_batch_offset(i) bytes into f,
- * with the single-instance layout. */
+ * with the single-instance layout.  rsl_batch_create applies rsl_step's CFL
+ * and stiffness guards to every (problem, dt[i]) and fails with
+ * RSL_EUNSTABLE when one of them fails (rsl_last_error names the instance). */
 typedef struct rsl_batch rsl_batch;
 int rsl_batch_create(const rsl_quad* const* quads, const rsl_problem* problems, const double* dt, int n,
                      rsl_batch** out);

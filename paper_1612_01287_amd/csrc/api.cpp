@@ -78,6 +78,31 @@ InstDesc make_desc(const rsl_quad* q, const rsl_problem* p, void* f, void* work,
     return d;
 }
 
+int check_stability(const rsl_quad* q, const rsl_problem* p, double dt) {
+    if (!(dt > 0.0 && std::isfinite(dt))) return set_error(RSL_EINVAL, "dt must be > 0");
+    const double kappa = p->kappa > 0 ? p->kappa : 2.0;
+    const bool force = p->flags & RSL_FLAG_FORCE_UNSTABLE;
+    if (p->problem == RSL_SOD) {
+        const double dz = (p->z_hi - p->z_lo) / p->nz;
+        const double vmax = std::fabs(q->xi.back());
+        if (dt * vmax / dz >= 1.0 && !force)
+            return set_error(RSL_EUNSTABLE, "CFL number dt*max|xi|/dz >= 1");
+    }
+    if (p->tau_mode != RSL_TAU_INF && !force) {
+        double tmin = p->tau_r;
+        if (p->tau_mode == RSL_TAU_ETAS) {
+            auto tau_of = [&](double n, double T) {
+                return p->tau_aw0 / T * (1.0 - 0.25 * std::log(n / (T * T * T) * (p->lambda_ref > 0 ? p->lambda_ref : 1.0)));
+            };
+            tmin = tau_of(p->n_L, p->T_L);
+            if (p->problem == RSL_SOD) tmin = std::min(tmin, tau_of(p->n_R, p->T_R));
+        }
+        if (!(dt <= kappa * tmin))
+            return set_error(RSL_EUNSTABLE, "dt exceeds kappa * tau_AW (stiff relaxation); set RSL_FLAG_FORCE_UNSTABLE to override");
+    }
+    return RSL_OK;
+}
+
 }  // namespace rsl
 
 using namespace rsl;
@@ -260,27 +285,7 @@ int rsl_step(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_de
     if (rc || (rc = check_problem(q, p))) return rc;
     if (!f_dev || !work_dev || !t) return set_error(RSL_EINVAL, "null argument");
     if (nsteps < 0) return set_error(RSL_EINVAL, "nsteps < 0");
-    if (!pos(dt)) return set_error(RSL_EINVAL, "dt must be > 0");
-    const double kappa = p->kappa > 0 ? p->kappa : 2.0;
-    const bool force = p->flags & RSL_FLAG_FORCE_UNSTABLE;
-    if (p->problem == RSL_SOD) {
-        const double dz = (p->z_hi - p->z_lo) / p->nz;
-        const double vmax = std::fabs(q->xi.back());
-        if (dt * vmax / dz >= 1.0 && !force)
-            return set_error(RSL_EUNSTABLE, "CFL number dt*max|xi|/dz >= 1");
-    }
-    if (p->tau_mode != RSL_TAU_INF && !force) {
-        double tmin = p->tau_r;
-        if (p->tau_mode == RSL_TAU_ETAS) {
-            auto tau_of = [&](double n, double T) {
-                return p->tau_aw0 / T * (1.0 - 0.25 * std::log(n / (T * T * T) * (p->lambda_ref > 0 ? p->lambda_ref : 1.0)));
-            };
-            tmin = tau_of(p->n_L, p->T_L);
-            if (p->problem == RSL_SOD) tmin = std::min(tmin, tau_of(p->n_R, p->T_R));
-        }
-        if (!(dt <= kappa * tmin))
-            return set_error(RSL_EUNSTABLE, "dt exceeds kappa * tau_AW (stiff relaxation); set RSL_FLAG_FORCE_UNSTABLE to override");
-    }
+    if ((rc = check_stability(q, p, dt))) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     InstDesc d = make_desc(q, p, f_dev, work_dev, dt);
     if (p->problem == RSL_SOD) {

@@ -281,7 +281,8 @@ int rsl_batch_create(const rsl_quad* const* quads, const rsl_problem* problems, 
         else {
             size_t fb = 0, wb = 0;
             rc = rsl_sizes(q, &p, &fb, &wb);
-            if (rc == RSL_OK && !(dt[i] > 0.0 && std::isfinite(dt[i]))) rc = set_error(RSL_EINVAL, "dt must be > 0");
+            if (rc == RSL_OK && (rc = check_stability(q, &p, dt[i])))
+                set_error(rc, "batch instance " + std::to_string(i) + ": " + rsl_last_error());
             if (rc == RSL_OK) {
                 b->quads.push_back(q);
                 b->probs.push_back(p);

@@ -115,7 +115,7 @@ __device__ void bj_run(const InstDesc& d, double tau0, double dtau, int nsteps, 
         __syncthreads();
         bj_L<Tf>(d, f2, t + 0.5 * dtau, L, red, bad);
         for (int v = threadIdx.x; v < d.V; v += blockDim.x)
-            f[v] = (double)(Tf)(f[v] / 3.0 + 2.0 * f2[v] / 3.0 + 2.0 * dtau * L[v] / 3.0);
+            f[v] = (double)(Tf)(kThird * f[v] + kTwoThirds * (f2[v] + dtau * L[v]));
         __syncthreads();
     }
     for (int v = threadIdx.x; v < d.V; v += blockDim.x) {

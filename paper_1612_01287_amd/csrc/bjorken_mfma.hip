@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
                             L -= (f - feq) * itaw;
                             if (st == 1) o = (double)(Tf)(fn[u][r] + dti * L);
                             else if (st == 2) o = (double)(Tf)(0.75 * fn[u][r] + 0.25 * f + 0.25 * dti * L);
-                            else o = (double)(Tf)(fn[u][r] / 3.0 + 2.0 * f / 3.0 + 2.0 * dti * L / 3.0);
+                            else o = (double)(Tf)(kThird * fn[u][r] + kTwoThirds * (f + dti * L));
                         }
                         out[u][r] = o;
                     }

@@ -168,6 +168,8 @@ void series_tables(std::vector<double>& ser, std::vector<double>& thr) {
             }
             cthr[nt] = (double)lo;
         }
+        // more terms never need a smaller beta^2: keep the table ascending
+        for (int nt = 2; nt < NT; ++nt) cthr[nt] = std::max(cthr[nt], cthr[nt - 1]);
     });
     ser = cser;
     thr = cthr;

@@ -12,6 +12,9 @@
 
 namespace rsl {
 
+// Stage-3 weights of the TVD RK3 scheme (eq. rk3), as products instead of divisions.
+constexpr double kThird = 1.0 / 3.0;
+constexpr double kTwoThirds = 2.0 / 3.0;
 // Largest N_Omega with equilibrium coefficients (App. A gives m <= 6).
 constexpr int kMaxNOm = 6;
 // Terms kept in the Maclaurin tables of K_{3,m}, K_{4,m} (see rsl_math.h).
@@ -128,6 +131,9 @@ struct WorkLayout {
 };
 WorkLayout work_layout(const rsl_quad* q, const rsl_problem* p);
 InstDesc make_desc(const rsl_quad* q, const rsl_problem* p, void* f, void* work, double dt);
+// CFL and relaxation-stiffness guards of one step of size dt (RSL_EUNSTABLE
+// unless RSL_FLAG_FORCE_UNSTABLE is set).
+int check_stability(const rsl_quad* q, const rsl_problem* p, double dt);
 
 // Kernel launchers (sod.hip, bjorken.hip).
 int launch_boundary_states(const InstDesc& d, double nL, double TL, double nR, double TR,

@@ -67,11 +67,16 @@ __device__ __forceinline__ int series_terms(double x, const double* __restrict__
     return nt;
 }
 
-// The same count for a wave-uniform x, through scalar loads.
+// The same count for a wave-uniform x (binary search; thr typically a copy in LDS).
 __device__ __forceinline__ int series_terms_uniform(double x, const double* __restrict__ thr) {
-    int nt = 1;
-    while (nt < kSeriesTerms && x > ((const __attribute__((address_space(4))) double*)thr)[nt]) ++nt;
-    return nt;
+    const double* t = thr;
+    int lo = 1, hi = kSeriesTerms;      // first nt in [1, kSeriesTerms) with x <= thr[nt], else kSeriesTerms
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (x > t[mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
 }
 
 // Largest x over the 64 lanes of a wave (all lanes active), as a wave-uniform value.
@@ -85,8 +90,8 @@ __device__ __forceinline__ double wave_max_uniform(double x) {
 
 // K_{3,m}, K_{4,m} for m = 0..nom (nom <= kMaxNOm); nt terms of the series
 // when |beta| < beta_s (nt from series_terms for beta^2 or anything larger:
-// extra terms only add values below the last bit).  The coefficient loop is
-// uniform when nt is, so the table comes through scalar loads.
+// extra terms only add values below the last bit).  ser is the term-major
+// coefficient table, in global memory or staged in LDS by the caller.
 __device__ __forceinline__ void kint(double beta, int nom, double beta_s, const double* __restrict__ ser,
                                      int nt, double* K3, double* K4) {
     const double ab = fabs(beta);
@@ -97,8 +102,7 @@ __device__ __forceinline__ void kint(double beta, int nom, double beta_s, const 
         for (int m = 0; m <= kMaxNOm; ++m) s3[m] = s4[m] = 0.0;
         double p = 1.0;
         for (int i = 0; i < nt; ++i) {
-            const __attribute__((address_space(4))) double* a =
-                (const __attribute__((address_space(4))) double*)ser + (size_t)i * 2 * (kMaxNOm + 1);
+            const double* a = ser + i * 2 * (kMaxNOm + 1);
 #pragma unroll
             for (int m = 0; m <= kMaxNOm; ++m) {
                 if (m <= nom) {

@@ -26,12 +26,27 @@ namespace rsl {
 
 namespace {
 
-constexpr int kCellUnroll = 8;  // stage-field loads per wave in flight in the cell kernel
+constexpr int kCellUnroll = 16;  // stage-field loads per wave in flight in the cell kernel
+
+constexpr int kSerLen = kSeriesTerms * 2 * (kMaxNOm + 1);
+
+// Shared memory of the cell kernel: partial moments of the waves, and copies
+// of the Maclaurin tables (read by wave 0 with uniform addresses; staging
+// them once per workgroup keeps table misses off the per-cell chain).
+template <int WC>
+struct CellLds {
+    double red[WC * 5 * kLanes];
+    double ser[kSerLen];
+    double thr[kSeriesTerms];
+};
 
 // WC waves split the velocity sum of 63 cells (one lane per cell).
 template <typename Tf, int STAGE, int WC>
-__device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, double* red) {
+__device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, CellLds<WC>& sh) {
     constexpr int W = WC, U = kCellUnroll;
+    double* red = sh.red;
+    for (int e = threadIdx.x; e < kSerLen; e += WC * kLanes) sh.ser[e] = d.tab.ser[e];
+    for (int e = threadIdx.x; e < kSeriesTerms; e += WC * kLanes) sh.thr[e] = d.tab.thr[e];
     const int lane = threadIdx.x & (kLanes - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     const int c = tile * kTileCells + lane;
@@ -82,7 +97,7 @@ __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, double* r
     if (!live || !cs.ok) {
         cs.n = 1.0; cs.T = 1.0; cs.beta = 0.0; cs.gamma = 1.0;
     }
-    const int nt = series_terms_uniform(wave_max_uniform(cs.beta * cs.beta), d.tab.thr);
+    const int nt = series_terms_uniform(wave_max_uniform(cs.beta * cs.beta), sh.thr);
     double tau = d.tau_r;
     if (d.tau_mode == RSL_TAU_ETAS) {
         const double lam = cs.n / (cs.T * cs.T * cs.T);
@@ -90,7 +105,7 @@ __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, double* r
     }
     const double it = 1.0 / tau;
     double c0[kMaxNOm + 1], c1[kMaxNOm + 1];
-    feq_coef(cs.n, cs.T, cs.beta, cs.gamma, d.T0, d.NOm, d.beta_series, d.tab.ser, nt, c0, c1);
+    feq_coef(cs.n, cs.T, cs.beta, cs.gamma, d.T0, d.NOm, d.beta_series, sh.ser, nt, c0, c1);
     if (!live) return;
     double* out = d.cell + c;
     out[0] = cs.gamma * it;
@@ -201,7 +216,7 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
                 double out;
                 if (STAGE == 1) out = y;
                 else if (STAGE == 2) out = 0.75 * (double)rn[i] + 0.25 * y;
-                else out = (double)rn[i] / 3.0 + 2.0 * y / 3.0;
+                else out = fma(kTwoThirds, y, kThird * (double)rn[i]);
                 if (out_lane) {
                     const Tf o = (Tf)out;
                     if (!isfinite((double)o)) bad |= 2u;
@@ -215,23 +230,23 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
 
 template <typename Tf, int STAGE, int WC>
 __global__ void __launch_bounds__(WC * 64) cell_single_kernel(InstDesc d, int ntiles) {
-    __shared__ double red[WC * 5 * kLanes];
+    __shared__ CellLds<WC> sh;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles || d.tau_mode == RSL_TAU_INF) return;
-    cell_tile<Tf, STAGE, WC>(d, tile, red);
+    cell_tile<Tf, STAGE, WC>(d, tile, sh);
 }
 
 template <typename Tf, int STAGE, int WC>
 __global__ void __launch_bounds__(WC * 64) cell_batch_kernel(const InstDesc* __restrict__ descs,
                                                             const int2* __restrict__ items, char* fbase,
                                                             char* wbase) {
-    __shared__ double red[WC * 5 * kLanes];
+    __shared__ CellLds<WC> sh;
     const int2 it = items[blockIdx.x];
     if (it.x < 0) return;
     InstDesc d = descs[it.x];
     if (d.tau_mode == RSL_TAU_INF) return;
     rebase(d, fbase, wbase);
-    cell_tile<Tf, STAGE, WC>(d, it.y, red);
+    cell_tile<Tf, STAGE, WC>(d, it.y, sh);
 }
 
 template <typename Tf, int STAGE, int W, int NV>

@@ -316,7 +316,7 @@ __device__ __forceinline__ void stage_tile(const InstDesc& d, int tile, char* ld
             double out;
             if (STAGE == 1) out = y;
             else if (STAGE == 2) out = 0.75 * (double)rn[i] + 0.25 * y;
-            else out = (double)rn[i] / 3.0 + 2.0 * y / 3.0;
+            else out = fma(kTwoThirds, y, kThird * (double)rn[i]);
             if (out_lane && valid) {
                 const Tf o = (Tf)out;
                 if (!isfinite((double)o)) bad |= 2u;

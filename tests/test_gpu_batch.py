@@ -270,3 +270,16 @@ def test_bjorken_matrix_cores_vs_oracle(rsl):
         ref, _ = Bo.run(Bo.init(), 1.0, 1e-3, 400)
         got = B.f(i).cpu().numpy().reshape(-1)
         assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-12, i
+
+
+def test_batch_rejects_unstable_steps(rsl):
+    """rsl_batch_create applies the CFL and stiffness guards of rsl_step to every instance."""
+    quad = rsl.Quadrature(3, 8, 3)
+    ok = rsl.make_problem(nz=100, tau_r=0.01)
+    stiff = rsl.make_problem(nz=100, tau_r=1e-4)
+    with pytest.raises(RuntimeError, match="instance 1"):
+        rsl.Batch([quad, quad], [ok, stiff], [0.004, 0.004])
+    with pytest.raises(RuntimeError, match="CFL"):
+        rsl.Batch([quad], [ok], [0.02])
+    forced = rsl.make_problem(nz=100, tau_r=1e-4, force=True)
+    rsl.Batch([quad, quad], [ok, forced], [0.004, 0.004])
