@@ -43,6 +43,7 @@ struct rsl_batch {
     size_t mfma_lds = 0;
     bool use_mfma = false;
     int bj_path = -1;             // -1 automatic, 0 per-instance kernel, 1 matrix cores
+    int ql_first[5] = {}, ql_count[5] = {};   // groups of each Q_L (1..4)
 };
 
 namespace rsl {
@@ -89,12 +90,15 @@ std::vector<int2> schedule(const rsl_batch* b, int cls, int tc) {
 
 }  // namespace
 
-// Bjorken groups: instances sharing one rsl_quad, 16 per group.
+// Bjorken groups: instances sharing one rsl_quad, 16 per group; groups of one
+// Q_L are contiguous (one launch each), costliest (largest Q_xi) first.
 std::vector<int> bj_groups(const rsl_batch* b) {
     std::vector<int> order(b->n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-        return b->quads[a]->Q != b->quads[c]->Q ? b->quads[a]->Q > b->quads[c]->Q : b->quads[a] < b->quads[c];
+        const rsl_quad *qa = b->quads[a], *qc = b->quads[c];
+        if (qa->QL != qc->QL) return qa->QL < qc->QL;
+        return qa->Q != qc->Q ? qa->Q > qc->Q : qa < qc;
     });
     std::vector<int> g;
     for (size_t s = 0; s < order.size();) {
@@ -130,6 +134,11 @@ int batch_upload(rsl_batch* b) {
         if (b->use_mfma) {
             groups = bj_groups(b);
             b->ngroups = (int)groups.size() / 16;
+            for (int g = 0; g < b->ngroups; ++g) {
+                const int ql = b->quads[groups[16 * g]]->QL;
+                if (b->ql_count[ql] == 0) b->ql_first[ql] = g;
+                ++b->ql_count[ql];
+            }
             for (int i = 0; i < b->n; ++i)
                 b->mfma_lds = std::max(b->mfma_lds, bj_mfma_lds_bytes(b->quads[i]->Q, b->quads[i]->QL));
             total += align_up(sizeof(int) * groups.size(), 256);
@@ -239,10 +248,15 @@ int batch_steps(rsl_batch* b, char* f, char* w, int nsteps, hipStream_t s) {
         if (nsteps > 0) rc = batch_sod_steps(b, f, w, nsteps, s);
     } else if (nsteps > 0) {
         const bool mfma = b->use_mfma && b->bj_path != 0;
-        if (mfma)
-            rc = launch_bj_mfma((const InstDesc*)b->dmem, b->groups, b->ngroups, b->mfma_lds, b->dtype, f, w, nsteps, s);
-        else
+        if (mfma) {
+            for (int ql = 1; ql <= 4 && rc == RSL_OK; ++ql) {
+                if (b->ql_count[ql] == 0) continue;
+                rc = launch_bj_mfma((const InstDesc*)b->dmem, b->groups + 16 * b->ql_first[ql], b->ql_count[ql], ql,
+                                    b->mfma_lds, b->dtype, f, w, nsteps, s);
+            }
+        } else {
             rc = launch_bj_batch_steps((const InstDesc*)b->dmem, b->n, b->bj_lds, b->dtype, f, w, 0.0, 0.0, nsteps, s);
+        }
     }
     return rc;
 }

@@ -9,11 +9,12 @@
 // K^L term (Q_L x Q_L, eq. K_lag_disc), the moments, the relaxation and the
 // RK3 combination (eq. rk3, stage times of Table II) run on the vector units.
 //
-// One workgroup (4 waves) owns one group for all requested steps: the stage
+// One workgroup (8 waves) owns one group for all requested steps: the stage
 // field F lives in LDS (row j, column i Q_L + k), f_n in registers in the
-// accumulator layout of the tiles each wave owns, K^P streams from global
-// memory pre-arranged in A-operand tile order (one coalesced 512-byte load
-// per wave and k-step).
+// accumulator layout of the row blocks each wave owns, K^P streams from
+// global memory pre-arranged in A-operand tile order (one coalesced 512-byte
+// load per wave and k-step, issued one k-step ahead and shared by the Q_L
+// column tiles of the row block).
 #include <hip/hip_runtime.h>
 
 #include "rsl_math.h"
@@ -23,25 +24,51 @@ namespace rsl {
 namespace {
 
 constexpr int kGI = 16;        // instances per group
-constexpr int kBW = 4;         // waves per workgroup
-constexpr int kMaxTilesPerWave = 16;
+constexpr int kBW = 8;         // waves per workgroup
+constexpr int kTPI = kBW * 64 / kGI;   // threads per instance in the moment sums
+constexpr int kMaxRB = 2;      // 16-row blocks of K^P F per wave (Q_xi <= 256)
+constexpr int kMaxCT = 4;      // 16-column tiles per row block (Q_L <= 4)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <typename Tf>
+// Orders one wave's LDS accesses (LDS executes a wave's instructions in issue
+// order, so keeping the compiler from moving them across is enough).
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename Tf, int QL>
 __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __restrict__ descs,
                                                            const int* __restrict__ groups, char* fbase,
                                                            char* wbase, int nsteps) {
-    extern __shared__ double X[];   // [Qp][NC] stage field, then per-instance scalars
+    extern __shared__ double X[];   // [Qp][NC] stage field, then per-instance scalars and tables
     const int* gi = groups + blockIdx.x * kGI;
     const InstDesc d0 = descs[gi[0]];
-    const int Q = d0.Q, QL = d0.QL, NC = kGI * QL;
+    constexpr int NC = kGI * QL, CT = QL;      // one 16-column tile per radial node
+    const int Q = d0.Q;
     const int Qp = (Q + 15) & ~15;
-    const int RT = Qp / 16, CT = NC / 16, KT = Qp / 4;
-    const int ntiles = RT * CT;
+    const int RT = Qp / 16, KT = Qp / 4;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    double* P = X + (size_t)Qp * NC;          // per instance: itaw, neq, th1, clock (4 x 16)
+    double* P = X + (size_t)Qp * NC;          // per instance: itaw, neq, th1, clock, dt (5 x 16)
+    // velocity-set tables read by the epilogue (from LDS, so that the
+    // compiler does not keep per-element copies in registers across steps)
+    double* Tx2 = P + 5 * kGI;                // [Qp]      xi_j^2
+    double* Tw = Tx2 + Qp;                    // [QL][Qp]  w_j w_k / 4
+    double* TL1 = Tw + (size_t)QL * Qp;       // [QL]      L_1(pbar_k)
+    double* TKL = TL1 + QL;                   // [QL][QL]  K^L
+    for (int e = threadIdx.x; e < Qp; e += blockDim.x) {
+        const double x = e < Q ? d0.tab.xi[e] : 0.0;
+        Tx2[e] = x * x;
+    }
+    for (int e = threadIdx.x; e < QL * Qp; e += blockDim.x) {
+        const int k = e / Qp, j = e - k * Qp;
+        Tw[e] = j < Q ? 0.25 * d0.tab.wxw[k * Q + j] : 0.0;
+    }
+    for (int e = threadIdx.x; e < QL; e += blockDim.x) TL1[e] = d0.tab.L1[e];
+    for (int e = threadIdx.x; e < QL * QL; e += blockDim.x) TKL[e] = d0.tab.KL[e];
 
     // ---- load the group's populations into LDS (padding rows/columns zero)
     for (int e = threadIdx.x; e < Qp * NC; e += blockDim.x) X[e] = 0.0;
@@ -58,35 +85,40 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
     }
     __syncthreads();
 
-    // ---- f_n in registers, accumulator layout: tile t = w + kBW*u, element r
-    //      sits at row 16*rt + lane/16 + 4*r, column 16*ct + lane%16 (the
-    //      v_mfma_f64_16x16x4f64 result layout, checked on the device)
-    double fn[kMaxTilesPerWave][4];
+    // ---- f_n in registers, accumulator layout: row block rb = w + kBW u,
+    //      column tile ct, element r at row 16 rb + lane/16 + 4 r, column
+    //      16 ct + lane%16 (the v_mfma_f64_16x16x4f64 result layout, checked
+    //      on the device)
+    double fn[kMaxRB][CT][4];
 #pragma unroll
-    for (int u = 0; u < kMaxTilesPerWave; ++u) {
-        const int t = w + kBW * u;
-        if (t < ntiles) {
-            const int rt = t / CT, ct = t - rt * CT;
+    for (int u = 0; u < kMaxRB; ++u) {
+        const int rb = w + kBW * u;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) fn[u][r] = X[(16 * rt + (lane >> 4) + 4 * r) * NC + 16 * ct + (lane & 15)];
-        }
+        for (int ct = 0; ct < CT; ++ct)
+            if (rb < RT) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) fn[u][ct][r] = X[(16 * rb + (lane >> 4) + 4 * r) * NC + 16 * ct + (lane & 15)];
+            }
     }
 
     const double* KPt = d0.tab.KPt;
     unsigned bad = 0;
-    if (threadIdx.x < kGI) P[3 * kGI + threadIdx.x] =
-        gi[threadIdx.x] >= 0 ? *((const double*)(wbase + (size_t)descs[gi[threadIdx.x]].clock)) : 1.0;
+    if (threadIdx.x < kGI) {
+        const bool live = gi[threadIdx.x] >= 0;
+        P[3 * kGI + threadIdx.x] = live ? *((const double*)(wbase + (size_t)descs[gi[threadIdx.x]].clock)) : 1.0;
+        P[4 * kGI + threadIdx.x] = live ? descs[gi[threadIdx.x]].dt : 0.0;
+    }
     __syncthreads();
 
     for (int it = 0; it < nsteps; ++it) {
 #pragma unroll 1
         for (int st = 1; st <= 3; ++st) {
-            // ---- per-instance moments and closure: 16 threads per instance
+            // ---- per-instance moments and closure: kTPI threads per instance
             {
-                const int i = threadIdx.x >> 4, sub = threadIdx.x & 15;
+                const int i = threadIdx.x / kTPI, sub = threadIdx.x % kTPI;
                 double n = 0.0, E = 0.0, PL = 0.0;
                 if (gi[i] >= 0)
-                    for (int e = sub; e < QL * Q; e += 16) {
+                    for (int e = sub; e < QL * Q; e += kTPI) {
                         const int j = e / QL, k = e - j * QL;
                         const double v = X[j * NC + i * QL + k], p = d0.tab.pk[k], x = d0.tab.xi[j];
                         n += v;
@@ -94,10 +126,10 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
                         PL += p * x * x * v;
                     }
 #pragma unroll
-                for (int o = 8; o > 0; o >>= 1) {
-                    n += __shfl_xor(n, o, 16);
-                    E += __shfl_xor(E, o, 16);
-                    PL += __shfl_xor(PL, o, 16);
+                for (int o = kTPI / 2; o > 0; o >>= 1) {
+                    n += __shfl_xor(n, o, kTPI);
+                    E += __shfl_xor(E, o, kTPI);
+                    PL += __shfl_xor(PL, o, kTPI);
                 }
                 if (sub == 0) {
                     double itaw = 0.0, neq = 0.0, th1 = 0.0;
@@ -130,60 +162,73 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
             }
             __syncthreads();
 
-            // ---- K^P F on the matrix cores, then the vector epilogue
-            double out[kMaxTilesPerWave][4];
+            // ---- K^P F on the matrix cores (one A fragment per k-step serves
+            //      every column tile of the row block; the next one is loaded
+            //      ahead)
+            d4 acc[kMaxRB][CT];
 #pragma unroll
-            for (int u = 0; u < kMaxTilesPerWave; ++u) {
-                const int t = w + kBW * u;
-                if (t < ntiles) {
-                    const int rt = t / CT, ct = t - rt * CT;
-                    d4 acc = {0.0, 0.0, 0.0, 0.0};
-                    const double* ap = KPt + ((size_t)rt * KT) * 64 + lane;
-                    const int bcol = 16 * ct + (lane & 15);
+            for (int u = 0; u < kMaxRB; ++u) {
+                const int rb = w + kBW * u;
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) acc[u][ct] = d4{0.0, 0.0, 0.0, 0.0};
+                if (rb < RT) {
+                    const double* ap = KPt + ((size_t)rb * KT) * 64 + lane;
+                    double a = ap[0];
                     for (int kk = 0; kk < KT; ++kk) {
-                        const double a = ap[(size_t)kk * 64];
-                        const double b = X[(4 * kk + (lane >> 4)) * NC + bcol];
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                        const double an = ap[(size_t)min(kk + 1, KT - 1) * 64];
+                        const double* brow = X + (4 * kk + (lane >> 4)) * NC + (lane & 15);
+#pragma unroll
+                        for (int ct = 0; ct < CT; ++ct)
+                                acc[u][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, brow[16 * ct], acc[u][ct], 0, 0, 0);
+                        a = an;
                     }
-                    const int col = bcol, i = col / QL, k = col - i * QL;
+                }
+            }
+            __syncthreads();   // every read of the stage field by the products is done
+
+            // ---- vector epilogue, in place: the rows of a row block belong to
+            //      one wave, which reads all of them before writing any
+#pragma unroll
+            for (int u = 0; u < kMaxRB; ++u) {
+                const int rb = w + kBW * u;
+                if (rb >= RT) continue;
+                double out[CT][4];
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                    const int col = 16 * ct + (lane & 15), i = col / QL, k = col - i * QL;
                     const bool live = gi[i] >= 0;
-                    const double dti = live ? descs[gi[i]].dt : 0.0;
+                    const double dti = P[4 * kGI + i];
                     // stage time of instance i (Table II)
                     const double tst = P[3 * kGI + i] + it * dti + (st == 1 ? 0.0 : (st == 2 ? dti : 0.5 * dti));
                     const double ti = 1.0 / tst;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int j = 16 * rt + (lane >> 4) + 4 * r;
+                        const int j = 16 * rb + (lane >> 4) + 4 * r;
                         double o = 0.0;
                         if (live && j < Q) {
                             const double f = X[j * NC + col];
                             double sl = 0.0;
-                            for (int kp = 0; kp < QL; ++kp) sl += d0.tab.KL[k * QL + kp] * X[j * NC + i * QL + kp];
-                            const double x = d0.tab.xi[j];
-                            double L = (-f + x * x * sl + acc[r]) * ti;
+                            for (int kp = 0; kp < QL; ++kp) sl += TKL[k * QL + kp] * X[j * NC + i * QL + kp];
+                            double L = (-f + Tx2[j] * sl + acc[u][ct][r]) * ti;
                             const double itaw = P[i], neq = P[kGI + i], th1 = P[2 * kGI + i];
-                            const double feq = d0.tab.wxw[k * Q + j] * 0.25 * neq * (1.0 + th1 * d0.tab.L1[k]);
+                            const double feq = Tw[k * Qp + j] * neq * (1.0 + th1 * TL1[k]);
                             L -= (f - feq) * itaw;
-                            if (st == 1) o = (double)(Tf)(fn[u][r] + dti * L);
-                            else if (st == 2) o = (double)(Tf)(0.75 * fn[u][r] + 0.25 * f + 0.25 * dti * L);
-                            else o = (double)(Tf)(kThird * fn[u][r] + kTwoThirds * (f + dti * L));
+                            if (st == 1) o = (double)(Tf)(fn[u][ct][r] + dti * L);
+                            else if (st == 2) o = (double)(Tf)(0.75 * fn[u][ct][r] + 0.25 * f + 0.25 * dti * L);
+                            else o = (double)(Tf)(kThird * fn[u][ct][r] + kTwoThirds * (f + dti * L));
                         }
-                        out[u][r] = o;
+                        out[ct][r] = o;
                     }
                 }
-            }
-            __syncthreads();   // every read of the stage field is done
+                wave_sync_lds();
 #pragma unroll
-            for (int u = 0; u < kMaxTilesPerWave; ++u) {
-                const int t = w + kBW * u;
-                if (t < ntiles) {
-                    const int rt = t / CT, ct = t - rt * CT;
+                for (int ct = 0; ct < CT; ++ct) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        X[(16 * rt + (lane >> 4) + 4 * r) * NC + 16 * ct + (lane & 15)] = out[u][r];
-                        if (st == 3) fn[u][r] = out[u][r];
+                        for (int r = 0; r < 4; ++r) {
+                            X[(16 * rb + (lane >> 4) + 4 * r) * NC + 16 * ct + (lane & 15)] = out[ct][r];
+                            if (st == 3) fn[u][ct][r] = out[ct][r];
+                        }
                     }
-                }
             }
             __syncthreads();
         }
@@ -211,29 +256,41 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
 
 size_t bj_mfma_lds_bytes(int Q, int QL) {
     const size_t Qp = (size_t)(Q + 15) / 16 * 16;
-    return sizeof(double) * (Qp * kGI * QL + 4 * kGI);
+    return sizeof(double) * (Qp * kGI * QL + 5 * kGI + Qp * (1 + QL) + QL + QL * QL);
 }
 
 bool bj_mfma_fits(int Q, int QL) {
-    const int tiles = (Q + 15) / 16 * QL;     // (Qp/16) x (16 QL / 16)
-    return QL >= 1 && QL <= 4 && tiles <= kBW * kMaxTilesPerWave && bj_mfma_lds_bytes(Q, QL) <= 150 * 1024;
+    const int RT = (Q + 15) / 16;
+    return QL >= 1 && QL <= kMaxCT && RT <= kBW * kMaxRB && bj_mfma_lds_bytes(Q, QL) <= 150 * 1024;
 }
 
-int launch_bj_mfma(const InstDesc* descs, const int* groups, int ngroups, size_t lds, int dtype, char* fbase,
-                   char* wbase, int nsteps, hipStream_t s) {
-    static const hipError_t a64 = hipFuncSetAttribute((const void*)bj_mfma_kernel<double>,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    static const hipError_t a32 = hipFuncSetAttribute((const void*)bj_mfma_kernel<float>,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    if (a64 != hipSuccess) return hip_check(a64, "hipFuncSetAttribute(bj_mfma_kernel)");
-    if (a32 != hipSuccess) return hip_check(a32, "hipFuncSetAttribute(bj_mfma_kernel)");
-    if (dtype == RSL_F64)
-        hipLaunchKernelGGL(bj_mfma_kernel<double>, dim3(ngroups), dim3(kBW * 64), lds, s, descs, groups, fbase, wbase,
-                           nsteps);
-    else
-        hipLaunchKernelGGL(bj_mfma_kernel<float>, dim3(ngroups), dim3(kBW * 64), lds, s, descs, groups, fbase, wbase,
-                           nsteps);
+template <typename Tf, int QL>
+int launch_bj_mfma_t(const InstDesc* descs, const int* groups, int ngroups, size_t lds, char* fbase, char* wbase,
+                     int nsteps, hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute((const void*)bj_mfma_kernel<Tf, QL>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    if (attr != hipSuccess) return hip_check(attr, "hipFuncSetAttribute(bj_mfma_kernel)");
+    hipLaunchKernelGGL((bj_mfma_kernel<Tf, QL>), dim3(ngroups), dim3(kBW * 64), lds, s, descs, groups, fbase, wbase,
+                       nsteps);
     return hip_check(hipGetLastError(), "bj_mfma_kernel launch");
+}
+
+template <typename Tf>
+int launch_bj_mfma_q(int QL, const InstDesc* descs, const int* groups, int ngroups, size_t lds, char* fbase,
+                     char* wbase, int nsteps, hipStream_t s) {
+    switch (QL) {
+        case 1: return launch_bj_mfma_t<Tf, 1>(descs, groups, ngroups, lds, fbase, wbase, nsteps, s);
+        case 2: return launch_bj_mfma_t<Tf, 2>(descs, groups, ngroups, lds, fbase, wbase, nsteps, s);
+        case 3: return launch_bj_mfma_t<Tf, 3>(descs, groups, ngroups, lds, fbase, wbase, nsteps, s);
+        case 4: return launch_bj_mfma_t<Tf, 4>(descs, groups, ngroups, lds, fbase, wbase, nsteps, s);
+        default: return set_error(RSL_EUNSUPPORTED, "matrix-core Bjorken path: Q_L > 4");
+    }
+}
+
+int launch_bj_mfma(const InstDesc* descs, const int* groups, int ngroups, int QL, size_t lds, int dtype, char* fbase,
+                   char* wbase, int nsteps, hipStream_t s) {
+    if (dtype == RSL_F64) return launch_bj_mfma_q<double>(QL, descs, groups, ngroups, lds, fbase, wbase, nsteps, s);
+    return launch_bj_mfma_q<float>(QL, descs, groups, ngroups, lds, fbase, wbase, nsteps, s);
 }
 
 }  // namespace rsl

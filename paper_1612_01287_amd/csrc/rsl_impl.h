@@ -154,7 +154,7 @@ int launch_bj_init(const InstDesc& d, double n0, double T0s, double tau0, hipStr
 size_t bj_lds_bytes(int V);
 size_t bj_mfma_lds_bytes(int Q, int QL);
 bool bj_mfma_fits(int Q, int QL);
-int launch_bj_mfma(const InstDesc* descs, const int* groups, int ngroups, size_t lds, int dtype, char* fbase,
+int launch_bj_mfma(const InstDesc* descs, const int* groups, int ngroups, int QL, size_t lds, int dtype, char* fbase,
                    char* wbase, int nsteps, hipStream_t s);
 int launch_bj_steps(const InstDesc& d, double tau0, double dtau, int nsteps, hipStream_t s);
 int launch_bj_moments(const InstDesc& d, const void* f, double* out, hipStream_t s);
