@@ -19,8 +19,9 @@ object carries three further measurements on seeded synthetic inputs:
            Q_xi in {8, 16, 32, 64}, T_L/T_R uniform in [1.1, 3], tau_r
            log-uniform in [1e-4, 1], dt = min(0.5/N_z, tau_r/2)), f in
            binary32, graph replays; 1.4 GB per field, so HBM-bound;
-  learned  the learned T^{mu nu} correction, scaled down (64 paired training
-           runs and 64 evaluation instances at N_z = 2048 instead of 8192):
+  learned  the learned T^{mu nu} correction, scaled down (128 paired training
+           runs x 5 snapshots = 1.3e6 samples, and 64 evaluation instances, at
+           N_z = 2048 instead of 8192):
            R-SLB(4;8) + features + network against the plain R-SLB(4;128)
            solve, wall time and relative T^{mu nu} error at t = 0.25.
 """
@@ -217,8 +218,8 @@ def ensemble_leg(torch, rsl, stream, n=1024, steps=20, chunk=10, seed=4):
 def learned_leg(torch, stream):
     from paper_1612_01287_amd import learned
     t0 = time.perf_counter()
-    X, T = learned.generate(n_runs=64, nz=2048, t_snaps=(0.05, 0.1, 0.15, 0.2, 0.25), seed=5, q_lo=8, q_hi=128)
-    corr, hist = learned.train(X, T, epochs=30, batch=4096, lr=2e-3, seed=1, margin=0.25)
+    X, T = learned.generate(n_runs=128, nz=2048, t_snaps=(0.05, 0.1, 0.15, 0.2, 0.25), seed=5, q_lo=8, q_hi=128)
+    corr, hist = learned.train(X, T, epochs=120, batch=8192, lr=2e-3, seed=1, margin=0.25)
     torch.cuda.synchronize()
     prep = time.perf_counter() - t0
     res = learned.evaluate(corr, n_inst=64, nz=2048, t_end=0.25, seed=6, q_lo=8, q_hi=128)

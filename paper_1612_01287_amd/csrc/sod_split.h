@@ -117,8 +117,10 @@ __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, CellLds<W
     }
 }
 
+// The W waves of a workgroup share one tile: its cells' coefficients are
+// loaded once into LDS (cf, kCellPar rows of 64) and read from there.
 template <typename Tf, int STAGE, int W, int NV>
-__device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp, char* lds) {
+__device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp, char* lds, double* cf) {
     constexpr int G = kGroup;
     constexpr int WN = kWin;
     const int vbase = grp * (W * NV);
@@ -152,20 +154,26 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
         rh[i] = lane < 5 ? row[hcc] : Tf(0);
         if (STAGE > 1) rn[i] = fn[(size_t)v * pitch + cc];
     }
-    // the lane's cell coefficients
+    // the tile's cell coefficients: the rows in use (gamma/tau, gamma beta/tau,
+    // c0[0..N_Omega], c1[0..N_Omega]) spread over the waves, through LDS
     const bool collide = d.tau_mode != RSL_TAU_INF;
     double cA = 0.0, cB = 0.0, c0[kMaxNOm + 1], c1[kMaxNOm + 1];
 #pragma unroll
     for (int m = 0; m <= kMaxNOm; ++m) c0[m] = c1[m] = 0.0;
     if (collide) {
-        const double* cp = d.cell + cc;
-        cA = cp[0];
-        cB = cp[pitch];
+        const int nrow = 2 + 2 * (d.NOm + 1);
+        for (int r = w; r < nrow; r += W) {
+            const int row = r < 2 + d.NOm + 1 ? r : r - (2 + d.NOm + 1) + 3 + kMaxNOm;
+            cf[row * kLanes + lane] = d.cell[(size_t)row * pitch + cc];
+        }
+        __syncthreads();
+        cA = cf[lane];
+        cB = cf[kLanes + lane];
 #pragma unroll
         for (int m = 0; m <= kMaxNOm; ++m)
             if (m <= d.NOm) {
-                c0[m] = cp[(2 + m) * pitch];
-                c1[m] = cp[(3 + kMaxNOm + m) * pitch];
+                c0[m] = cf[(2 + m) * kLanes + lane];
+                c1[m] = cf[(3 + kMaxNOm + m) * kLanes + lane];
             }
     }
 
@@ -249,24 +257,30 @@ __global__ void __launch_bounds__(WC * 64) cell_batch_kernel(const InstDesc* __r
     cell_tile<Tf, STAGE, WC>(d, it.y, sh);
 }
 
+template <typename Tf, int W>
+struct StreamLds {
+    Tf win[W * 2 * kGroup * kWin];
+    double cf[kCellPar * kLanes];
+};
+
 template <typename Tf, int STAGE, int W, int NV>
 __global__ void __launch_bounds__(W * 64) stream_single_kernel(InstDesc d, int ntiles) {
-    __shared__ Tf win[W * 2 * kGroup * kWin];
+    __shared__ StreamLds<Tf, W> sh;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
-    stream_tile<Tf, STAGE, W, NV>(d, tile, blockIdx.y, (char*)win);
+    stream_tile<Tf, STAGE, W, NV>(d, tile, blockIdx.y, (char*)sh.win, sh.cf);
 }
 
 template <typename Tf, int STAGE, int W, int NV>
 __global__ void __launch_bounds__(W * 64) stream_batch_kernel(const InstDesc* __restrict__ descs,
                                                              const int2* __restrict__ items, char* fbase,
                                                              char* wbase) {
-    __shared__ Tf win[W * 2 * kGroup * kWin];
+    __shared__ StreamLds<Tf, W> sh;
     const int2 it = items[blockIdx.x];
     if (it.x < 0) return;
     InstDesc d = descs[it.x];
     rebase(d, fbase, wbase);
-    stream_tile<Tf, STAGE, W, NV>(d, it.y, blockIdx.y, (char*)win);
+    stream_tile<Tf, STAGE, W, NV>(d, it.y, blockIdx.y, (char*)sh.win, sh.cf);
 }
 
 // Two launches on one stream: the cell kernel (WC waves) over the 63-cell
