@@ -384,7 +384,8 @@ int launch_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStr
 // Variants of the two-kernel form (sod_split.h): stream-kernel waves W,
 // velocities per wave NV, cell-kernel waves WC; any V.
 #define RSL_SPLIT_VARIANTS(X) \
-    X(10, 4, 2, 8) X(11, 4, 4, 8) X(12, 4, 8, 8) X(13, 4, 2, 16) X(14, 4, 4, 16) X(15, 4, 8, 16)
+    X(10, 4, 2, 8) X(11, 4, 4, 8) X(12, 4, 8, 8) X(13, 4, 2, 16) X(14, 4, 4, 16) X(15, 4, 8, 16) \
+    X(16, 8, 2, 16) X(17, 8, 1, 16) X(18, 2, 4, 16)
 
 }  // namespace
 
