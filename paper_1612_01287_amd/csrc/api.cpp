@@ -193,9 +193,20 @@ int rsl_make_quadrature(int Q_L, int Q_xi, int N_L, int N_Omega, double T0, int 
             for (int j = 0; j < Q; ++j)
                 for (int k = 0; k < QL; ++k) vpd[o++] = (double)(k * Q + j);
         }
+        // one record of kVrec doubles per velocity: xi_j, p_k, L_1(pbar_k),
+        // w_j w_k, P_0..P_kMaxNOm(xi_j) (read with one scalar-load burst)
+        std::vector<double> vrec((size_t)V * kVrec, 0.0);
+        for (int v = 0; v < V; ++v) {
+            double* r = vrec.data() + (size_t)v * kVrec;
+            r[0] = xv[v];
+            r[1] = pv[v];
+            r[2] = l1v[v];
+            r[3] = wxw[v];
+            for (int m = 0; m <= q->NOm; ++m) r[4 + m] = Pv[(size_t)m * V + v];
+        }
         const std::vector<double>* parts[] = {&q->xi, &wxw, &pk, &L1, &q->Pm, &q->ser, &q->thr, &q->KL, &q->KP,
-                                              &xv, &pv, &l1v, &Pv, &KPt, &vpd};
-        constexpr int NP = 15;
+                                              &xv, &pv, &l1v, &Pv, &KPt, &vrec, &vpd};
+        constexpr int NP = 16;
         size_t off[NP], total = 0;
         for (int i = 0; i < NP; ++i) {
             off[i] = total;
@@ -224,7 +235,8 @@ int rsl_make_quadrature(int Q_L, int Q_xi, int N_L, int N_Omega, double T0, int 
         q->dev.l1v = (const double*)(b + off[11]);
         q->dev.Pv = (const double*)(b + off[12]);
         q->dev.KPt = (const double*)(b + off[13]);
-        q->dev.vperm = (const int*)(b + off[14]);
+        q->dev.vrec = (const double*)(b + off[14]);
+        q->dev.vperm = (const int*)(b + off[15]);
         q->on_device = true;
     }
     *out = q;

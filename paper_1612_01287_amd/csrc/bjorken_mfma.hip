@@ -52,13 +52,15 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
     const int RT = Qp / 16, KT = Qp / 4;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    double* P = X + (size_t)Qp * NC;          // per instance: itaw, neq, th1, clock, dt (5 x 16)
+    double* P = X + (size_t)Qp * NC;          // per instance: itaw, neq, th1, clock, dt, tau mode, gas,
+                                              // tau_r, tau_aw0, lambda_ref, T0 (11 x 16)
     // velocity-set tables read by the epilogue (from LDS, so that the
     // compiler does not keep per-element copies in registers across steps)
-    double* Tx2 = P + 5 * kGI;                // [Qp]      xi_j^2
+    double* Tx2 = P + 11 * kGI;               // [Qp]      xi_j^2
     double* Tw = Tx2 + Qp;                    // [QL][Qp]  w_j w_k / 4
     double* TL1 = Tw + (size_t)QL * Qp;       // [QL]      L_1(pbar_k)
     double* TKL = TL1 + QL;                   // [QL][QL]  K^L
+    double* Tpk = TKL + QL * QL;              // [QL]      p_k
     for (int e = threadIdx.x; e < Qp; e += blockDim.x) {
         const double x = e < Q ? d0.tab.xi[e] : 0.0;
         Tx2[e] = x * x;
@@ -69,6 +71,7 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
     }
     for (int e = threadIdx.x; e < QL; e += blockDim.x) TL1[e] = d0.tab.L1[e];
     for (int e = threadIdx.x; e < QL * QL; e += blockDim.x) TKL[e] = d0.tab.KL[e];
+    for (int e = threadIdx.x; e < QL; e += blockDim.x) Tpk[e] = d0.tab.pk[e];
 
     // ---- load the group's populations into LDS (padding rows/columns zero)
     for (int e = threadIdx.x; e < Qp * NC; e += blockDim.x) X[e] = 0.0;
@@ -104,9 +107,17 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
     const double* KPt = d0.tab.KPt;
     unsigned bad = 0;
     if (threadIdx.x < kGI) {
-        const bool live = gi[threadIdx.x] >= 0;
-        P[3 * kGI + threadIdx.x] = live ? *((const double*)(wbase + (size_t)descs[gi[threadIdx.x]].clock)) : 1.0;
-        P[4 * kGI + threadIdx.x] = live ? descs[gi[threadIdx.x]].dt : 0.0;
+        const int i = threadIdx.x;
+        const bool live = gi[i] >= 0;
+        const InstDesc& d = descs[live ? gi[i] : gi[0]];
+        P[3 * kGI + i] = live ? *((const double*)(wbase + (size_t)d.clock)) : 1.0;
+        P[4 * kGI + i] = live ? d.dt : 0.0;
+        P[5 * kGI + i] = (double)d.tau_mode;
+        P[6 * kGI + i] = (double)d.gas;
+        P[7 * kGI + i] = d.tau_r;
+        P[8 * kGI + i] = d.tau_aw0;
+        P[9 * kGI + i] = d.lambda_ref;
+        P[10 * kGI + i] = d.T0;
     }
     __syncthreads();
 
@@ -116,44 +127,45 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
             // ---- per-instance moments and closure: kTPI threads per instance
             {
                 const int i = threadIdx.x / kTPI, sub = threadIdx.x % kTPI;
-                double n = 0.0, E = 0.0, PL = 0.0;
+                double n = 0.0, E = 0.0;
                 if (gi[i] >= 0)
                     for (int e = sub; e < QL * Q; e += kTPI) {
                         const int j = e / QL, k = e - j * QL;
-                        const double v = X[j * NC + i * QL + k], p = d0.tab.pk[k], x = d0.tab.xi[j];
+                        const double v = X[j * NC + i * QL + k];
                         n += v;
-                        E += p * v;
-                        PL += p * x * x * v;
+                        E += Tpk[k] * v;
                     }
 #pragma unroll
                 for (int o = kTPI / 2; o > 0; o >>= 1) {
                     n += __shfl_xor(n, o, kTPI);
                     E += __shfl_xor(E, o, kTPI);
-                    PL += __shfl_xor(PL, o, kTPI);
                 }
                 if (sub == 0) {
                     double itaw = 0.0, neq = 0.0, th1 = 0.0;
                     if (gi[i] >= 0) {
-                        const InstDesc& d = descs[gi[i]];
+                        // the instance's parameters, staged in LDS at the start
+                        const int mode = (int)P[5 * kGI + i], gas = (int)P[6 * kGI + i];
+                        const double tau_r = P[7 * kGI + i], tau_aw0 = P[8 * kGI + i];
+                        const double lambda_ref = P[9 * kGI + i], T0 = P[10 * kGI + i];
                         const double P3 = E / 3.0;
                         double T = 1.0;
-                        if (d.tau_mode != RSL_TAU_INF) {
-                            if (d.gas == RSL_GAS_IDEAL) {
+                        if (mode != RSL_TAU_INF) {
+                            if (gas == RSL_GAS_IDEAL) {
                                 if (!(n > 0.0) || !(P3 > 0.0)) bad |= 1u;
                                 T = P3 / n;
                                 neq = n;
-                                double taw = d.tau_r;
-                                if (d.tau_mode == RSL_TAU_ETAS)
-                                    taw = d.tau_aw0 / T * (1.0 - 0.25 * log(n / (T * T * T) * d.lambda_ref));
+                                double taw = tau_r;
+                                if (mode == RSL_TAU_ETAS)
+                                    taw = tau_aw0 / T * (1.0 - 0.25 * log(n / (T * T * T) * lambda_ref));
                                 itaw = 1.0 / taw;
                             } else {
                                 if (!(P3 > 0.0)) bad |= 1u;
                                 T = sqrt(sqrt(P3));
                                 neq = T * T * T;
-                                itaw = 1.0 / (d.tau_mode == RSL_TAU_ETAS ? d.tau_aw0 / T : d.tau_r);
+                                itaw = 1.0 / (mode == RSL_TAU_ETAS ? tau_aw0 / T : tau_r);
                             }
                         }
-                        th1 = 1.0 - T / d.T0;
+                        th1 = 1.0 - T / T0;
                     }
                     P[0 * kGI + i] = itaw;
                     P[1 * kGI + i] = neq;
@@ -256,7 +268,7 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
 
 size_t bj_mfma_lds_bytes(int Q, int QL) {
     const size_t Qp = (size_t)(Q + 15) / 16 * 16;
-    return sizeof(double) * (Qp * kGI * QL + 5 * kGI + Qp * (1 + QL) + QL + QL * QL);
+    return sizeof(double) * (Qp * kGI * QL + 11 * kGI + Qp * (1 + QL) + 2 * QL + QL * QL);
 }
 
 bool bj_mfma_fits(int Q, int QL) {

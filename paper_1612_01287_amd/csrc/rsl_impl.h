@@ -19,6 +19,8 @@ constexpr double kTwoThirds = 2.0 / 3.0;
 constexpr int kMaxNOm = 6;
 // Terms kept in the Maclaurin tables of K_{3,m}, K_{4,m} (see rsl_math.h).
 constexpr int kSeriesTerms = 128;
+// Doubles per velocity record (QuadDev::vrec): 4 + kMaxNOm + 1 used, padded to 16.
+constexpr int kVrec = 16;
 // Cells per wavefront tile: 64 lanes carry 64 interface fluxes, 63 cells are updated.
 constexpr int kLanes = 64;
 constexpr int kTileCells = kLanes - 1;
@@ -44,6 +46,7 @@ struct QuadDev {
     const double* Pv;    // [(NOm+1)*V]  P_m(xi_j), row m
     const int* vperm;    // [V] velocities ordered by the sign of xi (negative, zero, positive):
                          // the 32-lane stage kernels pair vperm[2p], vperm[2p+1]
+    const double* vrec;  // [V][kVrec] per-velocity record: xi_j, p_k, L_1(pbar_k), w_j w_k, P_0..P_6(xi_j)
     const double* KPt;   // K^P zero-padded to Qp = 16 ceil(Q/16), in MFMA A-operand order:
                          // [rt][kk][lane] = K^P[16 rt + lane % 16][4 kk + lane / 16]
 };

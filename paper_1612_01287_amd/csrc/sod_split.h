@@ -136,7 +136,7 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
     const int hcc = min(max(hc, 0), d.nz - 1);
     const bool eqbc = d.bc == RSL_BC_EQ;
     const int V = d.V;
-    Tf* win = (Tf*)lds + w * 2 * G * WN;
+    Tf* win = (Tf*)lds + w * G * WN;          // one window per wave, reused group after group
 
     const Tf* __restrict__ fcur = (const Tf*)(STAGE == 1 ? d.f : (STAGE == 2 ? d.f1 : d.f2));
     Tf* __restrict__ fout = (Tf*)(STAGE == 1 ? d.f1 : (STAGE == 2 ? d.f2 : d.f));
@@ -156,10 +156,11 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
     }
     // the tile's cell coefficients: the rows in use (gamma/tau, gamma beta/tau,
     // c0[0..N_Omega], c1[0..N_Omega]) spread over the waves, through LDS
+    // (c0, c1 stay in LDS and are read per velocity: fewer registers, more
+    // waves per SIMD)
     const bool collide = d.tau_mode != RSL_TAU_INF;
-    double cA = 0.0, cB = 0.0, c0[kMaxNOm + 1], c1[kMaxNOm + 1];
-#pragma unroll
-    for (int m = 0; m <= kMaxNOm; ++m) c0[m] = c1[m] = 0.0;
+    double cA = 0.0, cB = 0.0;
+    const double* cfl = cf + lane;
     if (collide) {
         const int nrow = 2 + 2 * (d.NOm + 1);
         for (int r = w; r < nrow; r += W) {
@@ -167,14 +168,8 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
             cf[row * kLanes + lane] = d.cell[(size_t)row * pitch + cc];
         }
         __syncthreads();
-        cA = cf[lane];
-        cB = cf[kLanes + lane];
-#pragma unroll
-        for (int m = 0; m <= kMaxNOm; ++m)
-            if (m <= d.NOm) {
-                c0[m] = cf[(2 + m) * kLanes + lane];
-                c1[m] = cf[(3 + kMaxNOm + m) * kLanes + lane];
-            }
+        cA = cfl[0];
+        cB = cfl[kLanes];
     }
 
     const bool out_lane = !ghost && lane >= 1;
@@ -192,7 +187,7 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
                     fc = ghost ? (c < 0 ? gl : gr) : fc;
                     h = hghost ? (hc < 0 ? gl : gr) : h;
                 }
-                Tf* wb = win + (((i0 / G) & 1) * G + (i - i0)) * WN;
+                Tf* wb = win + (i - i0) * WN;
                 wb[lane + 2] = (Tf)fc;
                 if (lane < 2) wb[lane] = (Tf)h;
                 else if (lane < 5) wb[kLanes + lane] = (Tf)h;
@@ -203,8 +198,11 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
         for (int i = i0; i < i0 + G && i < NV; ++i) {
             const int v = vbase + w + i * W;
             if (v < V) {
-                const double x = ldc(d.tab.xv, v);
-                const Tf* wb = win + (((i0 / G) & 1) * G + (i - i0)) * WN;
+                // the velocity's constants: one contiguous record, scalar loads
+                const __attribute__((address_space(4))) double* vr =
+                    (const __attribute__((address_space(4))) double*)d.tab.vrec + (size_t)v * kVrec;
+                const double x = vr[0];
+                const Tf* wb = win + (i - i0) * WN;
                 double sv[6];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) sv[q] = (double)wb[lane + q];
@@ -214,11 +212,13 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
                 const double Fm = shift_up(F);
                 double y = (double)(Tf)(sv[2] + dt * (-(F - Fm) * dzi));
                 if (collide) {
-                    const double l1 = ldc(d.tab.l1v, v), wx = ldc(d.tab.wxw, v);
+                    const double l1 = vr[2], wx = vr[3];
                     double gsum = 0.0;
 #pragma unroll
                     for (int m = 0; m <= kMaxNOm; ++m)
-                        if (m <= d.NOm) gsum = fma(ldc(d.tab.Pv, m * V + v), fma(l1, c1[m], c0[m]), gsum);
+                        if (m <= d.NOm)
+                            gsum = fma(vr[4 + m], fma(l1, cfl[(3 + kMaxNOm + m) * kLanes], cfl[(2 + m) * kLanes]),
+                                       gsum);
                     y += dt * (cA - cB * x) * (wx * gsum - sv[2]);
                 }
                 double out;
@@ -232,6 +232,7 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
                 }
             }
         }
+        wave_lds_sync();   // the group's window reads are done before the next group writes
     }
     if (bad) atomicOr(d.status, bad);
 }
@@ -259,7 +260,7 @@ __global__ void __launch_bounds__(WC * 64) cell_batch_kernel(const InstDesc* __r
 
 template <typename Tf, int W>
 struct StreamLds {
-    Tf win[W * 2 * kGroup * kWin];
+    Tf win[W * kGroup * kWin];
     double cf[kCellPar * kLanes];
 };
 
