@@ -255,6 +255,37 @@ def test_bjorken_matrix_cores_match_vector_path(rsl, dtype, tol):
     assert rc == 0
 
 
+def test_bjorken_matrix_cores_mixed_radial_sets(rsl):
+    """One batch holding Q_L = 2, 3 and 4 velocity sets: one matrix-core launch
+    per Q_L, each group against the vector path to rounding."""
+    rng = np.random.default_rng(12)
+    qs, probs, dts = [], [], []
+    cache = {}
+    for i in range(40):
+        QL = int(rng.choice([2, 3, 4]))
+        Q = int(rng.choice([20, 33, 64, 150]))
+        if (QL, Q) not in cache:
+            cache[(QL, Q)] = rsl.Quadrature(QL, Q, 4)
+        es = float(np.exp(rng.uniform(np.log(0.01), np.log(10.0))))
+        qs.append(cache[(QL, Q)])
+        probs.append(rsl.make_problem(kind="bjorken", tau_mode="etas", tau_aw0=5 * 0.1973269804 * es / 0.25))
+        dts.append(1e-3)
+    A = rsl.Batch(qs, probs, dts)
+    B = rsl.Batch(qs, probs, dts)
+    A.set_path(0)
+    B.set_path(1)
+    A.init()
+    B.init()
+    A.step(120)
+    B.step(120)
+    torch.cuda.synchronize()
+    for i in range(len(probs)):
+        a = A.f(i).cpu().numpy()
+        b = B.f(i).cpu().numpy()
+        assert np.max(np.abs(a - b)) / np.max(np.abs(a)) < 1e-12, (i, qs[i].QL, qs[i].Q)
+    assert B.status()[0] == 0
+
+
 def test_bjorken_matrix_cores_vs_oracle(rsl):
     import oracle
     qs, probs, dts = _bj_ensemble(rsl, 5, seed=8, Qs=(40, 101))
