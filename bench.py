@@ -62,8 +62,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default stage-kernel variants")
     ap.add_argument("--variants", default=None,
                     help="comma-separated stage-kernel variant per velocity class (-1: empty); skips the autotuner")
-    ap.add_argument("--aux", default="all", choices=("none", "all"),
-                    help="also measure the Bjorken batch, the uneven Sod ensemble and the learned correction")
+    ap.add_argument("--aux", default="all", choices=("none", "all", "bjorken", "ensemble", "learned"),
+                    help="also measure the Bjorken batch, the uneven Sod ensemble and the learned correction "
+                         "(all), or one of them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy five times (the reference kernel for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -324,11 +325,12 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roof,
     }
-    if a.aux == "all":
+    if a.aux != "none":
+        legs = {"bjorken": lambda: bjorken_leg(torch, rsl, stream),
+                "ensemble": lambda: ensemble_leg(torch, rsl, stream),
+                "learned": lambda: learned_leg(torch, stream)}
         with torch.cuda.stream(stream):
-            out["aux"] = {"bjorken": bjorken_leg(torch, rsl, stream),
-                          "ensemble": ensemble_leg(torch, rsl, stream),
-                          "learned": learned_leg(torch, stream)}
+            out["aux"] = {k: fn() for k, fn in legs.items() if a.aux in ("all", k)}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.dtype)
     print(json.dumps(out))

@@ -111,8 +111,9 @@ std::vector<int> bj_groups(const rsl_batch* b) {
     return g;
 }
 
-// Tile widths of the stage kernel variants: index 0 -> 63 cells, 1 -> 31 cells.
-constexpr int kTileWidths[2] = {63, 31};
+// Tile widths of the stage kernel variants: index 0 -> 63 cells, 1 -> 31 cells;
+// index 2 -> the 64-cell tiles of the per-cell kernel.
+constexpr int kTileWidths[3] = {kTileCells, 31, kCellTile};
 
 int tw_index(int var) { return stage_variant_tile_cells(var) == kTileWidths[0] ? 0 : 1; }
 
@@ -124,7 +125,7 @@ void use_variant(StageClass& cl, int var) {
 }
 
 int batch_upload(rsl_batch* b) {
-    std::vector<std::vector<int2>> items(2 * kClasses);
+    std::vector<std::vector<int2>> items(3 * kClasses);
     size_t total = 0;
     std::vector<int> groups;
     if (b->kind == RSL_BJORKEN) {
@@ -146,9 +147,9 @@ int batch_upload(rsl_batch* b) {
     }
     if (b->kind == RSL_SOD)
         for (int c = 0; c < kClasses; ++c)
-            for (int t = 0; t < 2; ++t) {
-                items[2 * c + t] = schedule(b, c, kTileWidths[t]);
-                total += align_up(sizeof(int2) * items[2 * c + t].size(), 256);
+            for (int t = 0; t < 3; ++t) {
+                items[3 * c + t] = schedule(b, c, kTileWidths[t]);
+                total += align_up(sizeof(int2) * items[3 * c + t].size(), 256);
             }
     const size_t dbytes = align_up(sizeof(InstDesc) * b->n, 256);
     int rc = hip_check(hipMalloc(&b->dmem, dbytes + std::max<size_t>(total, 256)), "hipMalloc(batch)");
@@ -162,8 +163,8 @@ int batch_upload(rsl_batch* b) {
         cl.maxV = 0;
         for (int i = 0; i < b->n; ++i)
             if (b->kind == RSL_SOD && stage_class_of(b->quads[i]->V) == c) cl.maxV = std::max(cl.maxV, b->quads[i]->V);
-        for (int t = 0; t < 2 && rc == RSL_OK; ++t) {
-            const std::vector<int2>& it = items[2 * c + t];
+        for (int t = 0; t < 3 && rc == RSL_OK; ++t) {
+            const std::vector<int2>& it = items[3 * c + t];
             cl.items_tw[t] = (const int2*)((char*)b->dmem + off);
             cl.nitems_tw[t] = (int)it.size();
             if (!it.empty())

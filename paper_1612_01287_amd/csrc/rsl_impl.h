@@ -24,6 +24,8 @@ constexpr int kVrec = 16;
 // Cells per wavefront tile: 64 lanes carry 64 interface fluxes, 63 cells are updated.
 constexpr int kLanes = 64;
 constexpr int kTileCells = kLanes - 1;
+// Cells per tile of the per-cell kernel (no stencil there: one lane per cell).
+constexpr int kCellTile = kLanes;
 // LDS window per velocity plane: cells z0-3 .. z0+65 (69 values), padded.
 constexpr int kWin = 72;
 
@@ -90,15 +92,16 @@ __host__ __device__ inline void rebase(InstDesc& d, char* fbase, char* wbase) {
 
 // Work items of one velocity-set class (see stage_class_of) in a batch.  The
 // class runs one kernel variant (sod_stage.h); items exist for both tile
-// widths (63 and 31 cells) so that the autotuner can switch variants.
+// widths (63 and 31 cells) so that the autotuner can switch variants, and
+// for the 64-cell tiles of the two-kernel form's cell kernel.
 struct StageClass {
     int var;                 // kernel variant in use
     int maxV;                // largest velocity set of the class
     const InstDesc* descs;   // device [n]
     const int2* items;       // device items of the current tile width, (instance, tile) or (-1, -1)
     int nitems;
-    const int2* items_tw[2]; // [0]: 63-cell tiles, [1]: 31-cell tiles
-    int nitems_tw[2];
+    const int2* items_tw[3]; // [0]: 63-cell tiles, [1]: 31-cell tiles, [2]: 64-cell tiles
+    int nitems_tw[3];
 };
 
 // Velocity-set classes of a Sod batch: V <= 32, 64, 128, 256, 320, 384 (the

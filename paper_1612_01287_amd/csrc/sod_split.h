@@ -40,7 +40,7 @@ struct CellLds {
     double thr[kSeriesTerms];
 };
 
-// WC waves split the velocity sum of 63 cells (one lane per cell).
+// WC waves split the velocity sum of 64 cells (one lane per cell).
 template <typename Tf, int STAGE, int WC>
 __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, CellLds<WC>& sh) {
     constexpr int W = WC, U = kCellUnroll;
@@ -49,8 +49,8 @@ __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, CellLds<W
     for (int e = threadIdx.x; e < kSeriesTerms; e += WC * kLanes) sh.thr[e] = d.tab.thr[e];
     const int lane = threadIdx.x & (kLanes - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
-    const int c = tile * kTileCells + lane;
-    const bool live = lane < kTileCells && c < d.nz;
+    const int c = tile * kCellTile + lane;
+    const bool live = c < d.nz;
     const int cc = min(c, d.nz - 1);
     const Tf* __restrict__ fcur = (const Tf*)(STAGE == 1 ? d.f : (STAGE == 2 ? d.f1 : d.f2));
     const size_t pitch = (size_t)d.pitch;
@@ -284,8 +284,8 @@ __global__ void __launch_bounds__(W * 64) stream_batch_kernel(const InstDesc* __
     stream_tile<Tf, STAGE, W, NV>(d, it.y, blockIdx.y, (char*)sh.win, sh.cf);
 }
 
-// Two launches on one stream: the cell kernel (WC waves) over the 63-cell
-// tiles, then the stream kernel (W waves of NV velocities) over (tile,
+// Two launches on one stream: the cell kernel (WC waves) over 64-cell tiles,
+// then the stream kernel (W waves of NV velocities) over (63-cell tile,
 // velocity slice).  A batch class sizes the slice dimension by its largest V.
 template <typename Tf, int STAGE, int W, int NV, int WC>
 int launch_split_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s) {
@@ -293,12 +293,14 @@ int launch_split_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, 
         const int ntiles = (d->nz + kTileCells - 1) / kTileCells;
         const int nb = (ntiles + 7) / 8 * 8;
         const int ng = (d->V + W * NV - 1) / (W * NV);
-        hipLaunchKernelGGL((cell_single_kernel<Tf, STAGE, WC>), dim3(nb), dim3(WC * 64), 0, s, *d, ntiles);
+        const int nct = (d->nz + kCellTile - 1) / kCellTile;
+        hipLaunchKernelGGL((cell_single_kernel<Tf, STAGE, WC>), dim3((nct + 7) / 8 * 8), dim3(WC * 64), 0, s, *d,
+                           nct);
         hipLaunchKernelGGL((stream_single_kernel<Tf, STAGE, W, NV>), dim3(nb, ng), dim3(W * 64), 0, s, *d, ntiles);
     } else {
         const int ng = (cl->maxV + W * NV - 1) / (W * NV);
-        hipLaunchKernelGGL((cell_batch_kernel<Tf, STAGE, WC>), dim3(cl->nitems), dim3(WC * 64), 0, s, cl->descs,
-                           cl->items, fb, wb);
+        hipLaunchKernelGGL((cell_batch_kernel<Tf, STAGE, WC>), dim3(cl->nitems_tw[2]), dim3(WC * 64), 0, s,
+                           cl->descs, cl->items_tw[2], fb, wb);
         hipLaunchKernelGGL((stream_batch_kernel<Tf, STAGE, W, NV>), dim3(cl->nitems, ng), dim3(W * 64), 0, s,
                            cl->descs, cl->items, fb, wb);
     }
