@@ -13,8 +13,8 @@
 // field F lives in LDS (row j, column i Q_L + k), f_n in registers in the
 // accumulator layout of the row blocks each wave owns, K^P streams from
 // global memory pre-arranged in A-operand tile order (one coalesced 512-byte
-// load per wave and k-step, issued one k-step ahead and shared by the Q_L
-// column tiles of the row block).
+// load per wave, row block and k-step, issued four to eight k-steps ahead and
+// shared by the Q_L column tiles of the row block).
 #include <hip/hip_runtime.h>
 
 #include "rsl_math.h"
@@ -28,6 +28,11 @@ constexpr int kBW = 8;         // waves per workgroup
 constexpr int kTPI = kBW * 64 / kGI;   // threads per instance in the moment sums
 constexpr int kMaxRB = 2;      // 16-row blocks of K^P F per wave (Q_xi <= 256)
 constexpr int kMaxCT = 4;      // 16-column tiles per row block (Q_L <= 4)
+static_assert(kMaxRB == 2, "the product loop below is written for two row blocks per wave");
+// k-steps per block of A-fragment loads (divides Q_xi padded / 4); two at
+// Q_L = 4, whose accumulators and f_n leave fewer registers
+template <int QL>
+constexpr int kPD = QL >= 4 ? 2 : 4;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -53,10 +58,10 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     double* P = X + (size_t)Qp * NC;          // per instance: itaw, neq, th1, clock, dt, tau mode, gas,
-                                              // tau_r, tau_aw0, lambda_ref, T0 (11 x 16)
+                                              // tau_r, tau_aw0, lambda_ref, T0, 1 / stage time (12 x 16)
     // velocity-set tables read by the epilogue (from LDS, so that the
     // compiler does not keep per-element copies in registers across steps)
-    double* Tx2 = P + 11 * kGI;               // [Qp]      xi_j^2
+    double* Tx2 = P + 12 * kGI;               // [Qp]      xi_j^2
     double* Tw = Tx2 + Qp;                    // [QL][Qp]  w_j w_k / 4
     double* TL1 = Tw + (size_t)QL * Qp;       // [QL]      L_1(pbar_k)
     double* TKL = TL1 + QL;                   // [QL][QL]  K^L
@@ -170,29 +175,62 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
                     P[0 * kGI + i] = itaw;
                     P[1 * kGI + i] = neq;
                     P[2 * kGI + i] = th1;
+                    // stage time of the instance (Table II)
+                    const double dti = P[4 * kGI + i];
+                    P[11 * kGI + i] = 1.0 / (P[3 * kGI + i] + it * dti + (st == 1 ? 0.0 : (st == 2 ? dti : 0.5 * dti)));
                 }
             }
             __syncthreads();
 
-            // ---- K^P F on the matrix cores (one A fragment per k-step serves
-            //      every column tile of the row block; the next one is loaded
-            //      ahead)
+            // ---- K^P F on the matrix cores.  A wave's row blocks advance
+            //      together: the B fragments of a k-step (LDS) serve every row
+            //      block, the A fragment of a row block serves every column
+            //      tile, and the A fragments are loaded 2-8 k-steps ahead (K^P
+            //      comes from the L2 or HBM, far slower than one k-step).
             d4 acc[kMaxRB][CT];
 #pragma unroll
-            for (int u = 0; u < kMaxRB; ++u) {
-                const int rb = w + kBW * u;
+            for (int u = 0; u < kMaxRB; ++u)
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) acc[u][ct] = d4{0.0, 0.0, 0.0, 0.0};
-                if (rb < RT) {
-                    const double* ap = KPt + ((size_t)rb * KT) * 64 + lane;
-                    double a = ap[0];
-                    for (int kk = 0; kk < KT; ++kk) {
-                        const double an = ap[(size_t)min(kk + 1, KT - 1) * 64];
-                        const double* brow = X + (4 * kk + (lane >> 4)) * NC + (lane & 15);
+            if (w < RT) {
+                const bool two = w + kBW < RT;   // wave-uniform
+                const double* ap0 = KPt + ((size_t)w * KT) * 64 + lane;
+                const double* ap1 = KPt + ((size_t)(two ? w + kBW : w) * KT) * 64 + lane;
+                constexpr int PD = kPD<QL>;
+                double a0[PD], a1[PD];
+#pragma unroll
+                for (int p = 0; p < PD; ++p) {
+                    a0[p] = ap0[p * 64];
+                    a1[p] = ap1[p * 64];
+                }
+                // KT is a multiple of PD (Q_xi is padded to 16 rows)
+                for (int kb = 0; kb < KT; kb += PD) {
+                    const int kn = min(kb + PD, KT - PD);
+                    double n0[PD], n1[PD];
+#pragma unroll
+                    for (int p = 0; p < PD; ++p) {
+                        n0[p] = ap0[(size_t)(kn + p) * 64];
+                        n1[p] = ap1[(size_t)(kn + p) * 64];
+                    }
+#pragma unroll
+                    for (int p = 0; p < PD; ++p) {
+                        const double* brow = X + (4 * (kb + p) + (lane >> 4)) * NC + (lane & 15);
+                        double b[CT];
+#pragma unroll
+                        for (int ct = 0; ct < CT; ++ct) b[ct] = brow[16 * ct];
 #pragma unroll
                         for (int ct = 0; ct < CT; ++ct)
-                                acc[u][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, brow[16 * ct], acc[u][ct], 0, 0, 0);
-                        a = an;
+                            acc[0][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[p], b[ct], acc[0][ct], 0, 0, 0);
+                        if (two) {
+#pragma unroll
+                            for (int ct = 0; ct < CT; ++ct)
+                                acc[1][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[p], b[ct], acc[1][ct], 0, 0, 0);
+                        }
+                    }
+#pragma unroll
+                    for (int p = 0; p < PD; ++p) {
+                        a0[p] = n0[p];
+                        a1[p] = n1[p];
                     }
                 }
             }
@@ -210,9 +248,7 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
                     const int col = 16 * ct + (lane & 15), i = col / QL, k = col - i * QL;
                     const bool live = gi[i] >= 0;
                     const double dti = P[4 * kGI + i];
-                    // stage time of instance i (Table II)
-                    const double tst = P[3 * kGI + i] + it * dti + (st == 1 ? 0.0 : (st == 2 ? dti : 0.5 * dti));
-                    const double ti = 1.0 / tst;
+                    const double ti = P[11 * kGI + i];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int j = 16 * rb + (lane >> 4) + 4 * r;
@@ -268,7 +304,7 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
 
 size_t bj_mfma_lds_bytes(int Q, int QL) {
     const size_t Qp = (size_t)(Q + 15) / 16 * 16;
-    return sizeof(double) * (Qp * kGI * QL + 11 * kGI + Qp * (1 + QL) + 2 * QL + QL * QL);
+    return sizeof(double) * (Qp * kGI * QL + 12 * kGI + Qp * (1 + QL) + 2 * QL + QL * QL);
 }
 
 bool bj_mfma_fits(int Q, int QL) {
