@@ -208,6 +208,14 @@ int rsl_batch_moments(rsl_batch* b, const void* f_dev, void* work_dev, double* o
  * LDS), 0 one workgroup per instance on the vector units, 1 matrix cores
  * (RSL_EUNSUPPORTED if not available).  The two paths agree to rounding. */
 int rsl_batch_set_path(rsl_batch* b, int path);
+/* Matrix-core groups of a Bjorken batch, in launch order: *ngroups receives
+ * their number (0 when the batch has no matrix-core path) and, when sizes is
+ * not NULL, sizes[g] for g < min(*ngroups, cap) the number of instances in
+ * group g (1..16, all sharing one velocity set).  Groups are sized so that
+ * their estimated costs balance over the GPU's compute units: a group of fewer
+ * instances fills fewer 16-column tiles of the K^P F product (eq. K_leg_disc)
+ * and finishes sooner.  RSL_EINVAL for a NULL batch or ngroups, or cap < 0. */
+int rsl_batch_groups(const rsl_batch* b, int* ngroups, int* sizes, int cap);
 /* Stage-kernel variants.  One Sod RK3 stage (Sec. III F-G: moments, Landau
  * frame, f^eq, AW relaxation, WENO5 fluxes, RK combination) runs either as
  * one fused kernel per tile of cells or in a two-kernel form (a per-cell

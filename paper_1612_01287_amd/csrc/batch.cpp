@@ -10,6 +10,8 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <queue>
+#include <functional>
 #include <vector>
 
 #include "rsl_impl.h"
@@ -44,6 +46,7 @@ struct rsl_batch {
     bool use_mfma = false;
     int bj_path = -1;             // -1 automatic, 0 per-instance kernel, 1 matrix cores
     int ql_first[5] = {}, ql_count[5] = {};   // groups of each Q_L (1..4)
+    std::vector<int> group_sizes;             // live instances per group, launch order
 };
 
 namespace rsl {
@@ -90,9 +93,50 @@ std::vector<int2> schedule(const rsl_batch* b, int cls, int tc) {
 
 }  // namespace
 
-// Bjorken groups: instances sharing one rsl_quad, 16 per group; groups of one
-// Q_L are contiguous (one launch each), costliest (largest Q_xi) first.
-std::vector<int> bj_groups(const rsl_batch* b) {
+// Cost of one matrix-core Bjorken group on one CU, per RK stage, in units of
+// one v_mfma_f64_16x16x4f64 (64 cycles), fitted to measured stage times at
+// Q_xi = 40, 100, 200 with 1 and 3 column tiles: a part independent of the
+// column tiles (moments, closure, barriers) that grows with Q_xi, and per
+// column tile the k-steps of the busiest SIMD (waves w and w + 4 share a
+// SIMD; wave w owns row blocks w and w + 8) plus the vector epilogue.
+double bj_group_cost(int Q, int tiles) {
+    const int RT = (Q + 15) / 16, KT = 4 * RT;
+    int rb = 0;
+    for (int simd = 0; simd < 4; ++simd) {
+        int c = 0;
+        for (int w = simd; w < 8; w += 4)
+            for (int u = 0; u < 2; ++u) c += w + 8 * u < RT;
+        rb = std::max(rb, c);
+    }
+    const double q = std::max(Q - 40, 0);
+    return 84.0 + 1.22 * q + tiles * ((double)rb * KT + 31.0 + 0.2 * q);
+}
+
+// Longest-first list schedule of group costs on ncu CUs (one workgroup per
+// CU, dispatched in list order as CUs free up): its makespan.
+double bj_makespan(std::vector<double> cost, int ncu) {
+    std::sort(cost.begin(), cost.end(), std::greater<double>());
+    std::priority_queue<double, std::vector<double>, std::greater<double>> cu;
+    for (int k = 0; k < ncu; ++k) cu.push(0.0);
+    double span = 0.0;
+    for (double c : cost) {
+        const double t = cu.top() + c;
+        cu.pop();
+        cu.push(t);
+        span = std::max(span, t);
+    }
+    return span;
+}
+
+// Bjorken groups: instances sharing one rsl_quad, up to 16 per group, live
+// instances first (the kernel skips column tiles past the last live one);
+// groups of one Q_L are contiguous (one launch each), costliest first.  One
+// workgroup per group and per CU: when a few velocity sets are much larger
+// than the rest, their full groups would be the critical path of the launch,
+// so the instances of a set whose full group costs more than a cap are spread
+// over groups of fewer column tiles.  The cap (a multiple of the average load
+// per CU with full groups) is the one whose list schedule ends first.
+std::vector<int> bj_groups(const rsl_batch* b, int ncu) {
     std::vector<int> order(b->n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
@@ -100,13 +144,65 @@ std::vector<int> bj_groups(const rsl_batch* b) {
         if (qa->QL != qc->QL) return qa->QL < qc->QL;
         return qa->Q != qc->Q ? qa->Q > qc->Q : qa < qc;
     });
-    std::vector<int> g;
+    std::vector<std::pair<size_t, size_t>> sets;   // runs of one rsl_quad in `order`
     for (size_t s = 0; s < order.size();) {
-        const rsl_quad* q = b->quads[order[s]];
-        std::vector<int> grp;
-        while (s < order.size() && b->quads[order[s]] == q && grp.size() < 16) grp.push_back(order[s++]);
-        grp.resize(16, -1);
-        g.insert(g.end(), grp.begin(), grp.end());
+        size_t e = s;
+        while (e < order.size() && b->quads[order[e]] == b->quads[order[s]]) ++e;
+        sets.push_back({s, e});
+        s = e;
+    }
+    auto tiles_of = [](int n, int QL) { return (n * QL + 15) / 16; };
+    double total = 0.0;
+    for (auto& st : sets) {
+        const rsl_quad* q = b->quads[order[st.first]];
+        for (size_t m = st.second - st.first; m > 0; m -= std::min<size_t>(m, 16))
+            total += bj_group_cost(q->Q, tiles_of((int)std::min<size_t>(m, 16), q->QL));
+    }
+    ncu = std::max(ncu, 1);
+    struct G { int QL; double cost; size_t first; int n; };
+    auto make_plan = [&](double cap) {
+        std::vector<G> groups;
+        for (auto& st : sets) {
+            const rsl_quad* q = b->quads[order[st.first]];
+            const int m = (int)(st.second - st.first);
+            int per = std::min(16, 16 / q->QL);          // one column tile
+            for (int t = 2; t <= q->QL; ++t)
+                if (bj_group_cost(q->Q, t) <= cap) per = std::min(16, 16 * t / q->QL);
+            const int ng = (m + per - 1) / per;
+            for (int g = 0, s = 0; g < ng; ++g) {
+                const int n = m / ng + (g < m % ng);     // sizes as even as possible
+                groups.push_back({q->QL, bj_group_cost(q->Q, tiles_of(n, q->QL)), st.first + s, n});
+                s += n;
+            }
+        }
+        return groups;
+    };
+    auto span_of = [&](const std::vector<G>& groups) {
+        double span = 0.0;
+        for (int ql = 1; ql <= 4; ++ql) {      // one launch per Q_L, one after the other
+            std::vector<double> c;
+            for (const G& g : groups)
+                if (g.QL == ql) c.push_back(g.cost);
+            if (!c.empty()) span += bj_makespan(c, ncu);
+        }
+        return span;
+    };
+    std::vector<G> best;
+    double best_span = 0.0;
+    for (double mult : {1e30, 2.0, 1.6, 1.3, 1.15, 1.0}) {
+        std::vector<G> plan = make_plan(mult * total / ncu);
+        const double span = span_of(plan);
+        if (best.empty() || span < best_span * (1.0 - 1e-9)) {
+            best = std::move(plan);
+            best_span = span;
+        }
+    }
+    std::stable_sort(best.begin(), best.end(), [](const G& x, const G& y) {
+        return x.QL != y.QL ? x.QL < y.QL : x.cost > y.cost;
+    });
+    std::vector<int> g;
+    for (const G& gr : best) {
+        for (int k = 0; k < 16; ++k) g.push_back(k < gr.n ? order[gr.first + k] : -1);
     }
     return g;
 }
@@ -133,8 +229,15 @@ int batch_upload(rsl_batch* b) {
         for (int i = 0; i < b->n; ++i)
             if (!bj_mfma_fits(b->quads[i]->Q, b->quads[i]->QL)) b->use_mfma = false;
         if (b->use_mfma) {
-            groups = bj_groups(b);
+            int ncu = 0;
+            if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) ncu = 0;
+            groups = bj_groups(b, ncu > 0 ? ncu : 256);
             b->ngroups = (int)groups.size() / 16;
+            for (int g = 0; g < b->ngroups; ++g) {
+                int n = 0;
+                while (n < 16 && groups[16 * g + n] >= 0) ++n;
+                b->group_sizes.push_back(n);
+            }
             for (int g = 0; g < b->ngroups; ++g) {
                 const int ql = b->quads[groups[16 * g]]->QL;
                 if (b->ql_count[ql] == 0) b->ql_first[ql] = g;
@@ -441,6 +544,14 @@ int rsl_batch_set_path(rsl_batch* b, int path) {
     if (path == 1 && !b->use_mfma) return set_error(RSL_EUNSUPPORTED, "matrix-core path not available for this batch");
     b->bj_path = path;
     batch_drop_graph(b);
+    return RSL_OK;
+}
+
+int rsl_batch_groups(const rsl_batch* b, int* ngroups, int* sizes, int cap) {
+    if (!b || !ngroups || cap < 0) return set_error(RSL_EINVAL, "bad batch group query");
+    *ngroups = b->use_mfma ? b->ngroups : 0;
+    if (sizes)
+        for (int g = 0; g < std::min(*ngroups, cap); ++g) sizes[g] = b->group_sizes[g];
     return RSL_OK;
 }
 

@@ -29,12 +29,79 @@ constexpr int kTPI = kBW * 64 / kGI;   // threads per instance in the moment sum
 constexpr int kMaxRB = 2;      // 16-row blocks of K^P F per wave (Q_xi <= 256)
 constexpr int kMaxCT = 4;      // 16-column tiles per row block (Q_L <= 4)
 static_assert(kMaxRB == 2, "the product loop below is written for two row blocks per wave");
-// k-steps per block of A-fragment loads (divides Q_xi padded / 4); two at
-// Q_L = 4, whose accumulators and f_n leave fewer registers
-template <int QL>
-constexpr int kPD = QL >= 4 ? 2 : 4;
+// k-steps per block of A-fragment loads: deeper for fewer column tiles (less
+// matrix-core work per k-step to cover the latency, fewer accumulators),
+// shallower at Q_L = 4, whose accumulators and f_n leave fewer registers
+template <int QL, int NT>
+constexpr int kPD = QL >= 4 ? (NT == 1 ? 4 : 2) : (NT == 1 ? 8 : 4);
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+
+// K^P F over the first NT column tiles for row block w (and w + kBW when TWO)
+// of one wave: the row blocks advance together, so that the B fragments of a
+// k-step (LDS) serve both, and one A fragment serves every column tile; the A
+// fragments (K^P in A-operand tile order, from the L2 or HBM, far slower than
+// one k-step) are loaded 2-8 k-steps ahead.
+template <int QL, int NT, bool TWO, int CT>
+__device__ __forceinline__ void kp_product(d4 (&acc)[kMaxRB][CT], const double* X, const double* KPt, int w,
+                                           int lane, int KT) {
+    constexpr int NC = kGI * QL;
+    constexpr int PD = kPD<QL, NT>;
+    const double* ap0 = KPt + ((size_t)w * KT) * 64 + lane;
+    const double* ap1 = KPt + ((size_t)(w + (TWO ? kBW : 0)) * KT) * 64 + lane;
+    double a0[PD], a1[PD];
+#pragma unroll
+    for (int p = 0; p < PD; ++p) {
+        const size_t k0 = (size_t)min(p, KT - 1) * 64;
+        a0[p] = ap0[k0];
+        if (TWO) a1[p] = ap1[k0];
+    }
+    // KT is a multiple of 4 (Q_xi is padded to 16 rows); a block of 8 may
+    // overhang it by 4 (loads clamped, products skipped)
+    for (int kb = 0; kb < KT; kb += PD) {
+        double n0[PD], n1[PD];
+#pragma unroll
+        for (int p = 0; p < PD; ++p) {
+            const size_t kn = (size_t)min(kb + PD + p, KT - 1) * 64;
+            n0[p] = ap0[kn];
+            if (TWO) n1[p] = ap1[kn];
+        }
+#pragma unroll
+        for (int p = 0; p < PD; ++p) {
+            if (PD > 4 && kb + p >= KT) break;
+            const double* brow = X + (4 * (kb + p) + (lane >> 4)) * NC + (lane & 15);
+            double b[NT];
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) b[ct] = brow[16 * ct];
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct)
+                acc[0][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[p], b[ct], acc[0][ct], 0, 0, 0);
+            if (TWO) {
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+                    acc[1][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[p], b[ct], acc[1][ct], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < PD; ++p) {
+            a0[p] = n0[p];
+            if (TWO) a1[p] = n1[p];
+        }
+    }
+}
+
+// The product with the group's live column tiles (nct, wave-uniform) as a
+// compile-time count: no per-MFMA branches.
+template <int QL, bool TWO, int CT>
+__device__ __forceinline__ void kp_product_nt(d4 (&acc)[kMaxRB][CT], const double* X, const double* KPt, int w,
+                                              int lane, int KT, int nct) {
+    if (nct >= CT) kp_product<QL, CT, TWO>(acc, X, KPt, w, lane, KT);
+    else if (nct == 1) kp_product<QL, 1, TWO>(acc, X, KPt, w, lane, KT);
+    else if constexpr (CT > 2) {
+        if (nct == 2) kp_product<QL, 2, TWO>(acc, X, KPt, w, lane, KT);
+        else if constexpr (CT > 3) kp_product<QL, 3, TWO>(acc, X, KPt, w, lane, KT);
+    }
+}
 
 // Orders one wave's LDS accesses (LDS executes a wave's instructions in issue
 // order, so keeping the compiler from moving them across is enough).
@@ -57,6 +124,12 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
     const int RT = Qp / 16, KT = Qp / 4;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    // live instances come first in a group; column tiles past the last live
+    // column are skipped (groups smaller than 16 shorten the critical path of
+    // a batch with a few large velocity sets)
+    int nlive = 0;
+    while (nlive < kGI && gi[nlive] >= 0) ++nlive;
+    const int nct = __builtin_amdgcn_readfirstlane((nlive * QL + 15) / 16);
     double* P = X + (size_t)Qp * NC;          // per instance: itaw, neq, th1, clock, dt, tau mode, gas,
                                               // tau_r, tau_aw0, lambda_ref, T0, 1 / stage time (12 x 16)
     // velocity-set tables read by the epilogue (from LDS, so that the
@@ -182,11 +255,7 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
             }
             __syncthreads();
 
-            // ---- K^P F on the matrix cores.  A wave's row blocks advance
-            //      together: the B fragments of a k-step (LDS) serve every row
-            //      block, the A fragment of a row block serves every column
-            //      tile, and the A fragments are loaded 2-8 k-steps ahead (K^P
-            //      comes from the L2 or HBM, far slower than one k-step).
+            // ---- K^P F on the matrix cores
             d4 acc[kMaxRB][CT];
 #pragma unroll
             for (int u = 0; u < kMaxRB; ++u)
@@ -194,45 +263,8 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
                 for (int ct = 0; ct < CT; ++ct) acc[u][ct] = d4{0.0, 0.0, 0.0, 0.0};
             if (w < RT) {
                 const bool two = w + kBW < RT;   // wave-uniform
-                const double* ap0 = KPt + ((size_t)w * KT) * 64 + lane;
-                const double* ap1 = KPt + ((size_t)(two ? w + kBW : w) * KT) * 64 + lane;
-                constexpr int PD = kPD<QL>;
-                double a0[PD], a1[PD];
-#pragma unroll
-                for (int p = 0; p < PD; ++p) {
-                    a0[p] = ap0[p * 64];
-                    a1[p] = ap1[p * 64];
-                }
-                // KT is a multiple of PD (Q_xi is padded to 16 rows)
-                for (int kb = 0; kb < KT; kb += PD) {
-                    const int kn = min(kb + PD, KT - PD);
-                    double n0[PD], n1[PD];
-#pragma unroll
-                    for (int p = 0; p < PD; ++p) {
-                        n0[p] = ap0[(size_t)(kn + p) * 64];
-                        n1[p] = ap1[(size_t)(kn + p) * 64];
-                    }
-#pragma unroll
-                    for (int p = 0; p < PD; ++p) {
-                        const double* brow = X + (4 * (kb + p) + (lane >> 4)) * NC + (lane & 15);
-                        double b[CT];
-#pragma unroll
-                        for (int ct = 0; ct < CT; ++ct) b[ct] = brow[16 * ct];
-#pragma unroll
-                        for (int ct = 0; ct < CT; ++ct)
-                            acc[0][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[p], b[ct], acc[0][ct], 0, 0, 0);
-                        if (two) {
-#pragma unroll
-                            for (int ct = 0; ct < CT; ++ct)
-                                acc[1][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[p], b[ct], acc[1][ct], 0, 0, 0);
-                        }
-                    }
-#pragma unroll
-                    for (int p = 0; p < PD; ++p) {
-                        a0[p] = n0[p];
-                        a1[p] = n1[p];
-                    }
-                }
+                if (two) kp_product_nt<QL, true>(acc, X, KPt, w, lane, KT, nct);
+                else kp_product_nt<QL, false>(acc, X, KPt, w, lane, KT, nct);
             }
             __syncthreads();   // every read of the stage field by the products is done
 
@@ -246,7 +278,7 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) {
                     const int col = 16 * ct + (lane & 15), i = col / QL, k = col - i * QL;
-                    const bool live = gi[i] >= 0;
+                    const bool live = ct < nct && gi[i] >= 0;
                     const double dti = P[4 * kGI + i];
                     const double ti = P[11 * kGI + i];
 #pragma unroll

@@ -208,6 +208,7 @@ _sig("rsl_batch_step", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_stage", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_graph_step", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_set_path", ctypes.c_int, [_vp, ctypes.c_int])
+_sig("rsl_batch_groups", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.c_int])
 _sig("rsl_batch_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("rsl_batch_status", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)])
 _ip = ctypes.POINTER(ctypes.c_int)
@@ -268,6 +269,14 @@ class Batch:
     def set_path(self, path):
         """Bjorken batches: -1 automatic, 0 vector units, 1 matrix cores."""
         check(_lib.rsl_batch_set_path(self._h, int(path)))
+
+    def groups(self):
+        """Instances per matrix-core group of a Bjorken batch, in launch order."""
+        n = ctypes.c_int(0)
+        check(_lib.rsl_batch_groups(self._h, ctypes.byref(n), None, 0))
+        out = (ctypes.c_int * max(n.value, 1))()
+        check(_lib.rsl_batch_groups(self._h, ctypes.byref(n), out, n.value))
+        return list(out)[:n.value]
 
     def variant(self, cls):
         """(variant id or -1 for an empty class, largest V of the class)."""

@@ -286,6 +286,40 @@ def test_bjorken_matrix_cores_mixed_radial_sets(rsl):
     assert B.status()[0] == 0
 
 
+def test_bjorken_groups_of_every_tile_count(rsl):
+    """Velocity sets of very different sizes: the batch spreads the large sets
+    over groups of fewer instances (1, 2 or 3 of the 16-column tiles at
+    Q_L = 3) to balance the compute units; every instance still agrees with
+    the vector path to rounding, whatever the size of its group."""
+    rng = np.random.default_rng(21)
+    quads, qs, probs, dts = {}, [], [], []
+    for _ in range(1500):
+        Q = int(rng.integers(20, 201))
+        if Q not in quads:
+            quads[Q] = rsl.Quadrature(3, Q, 4)
+        es = float(np.exp(rng.uniform(np.log(0.01), np.log(10.0))))
+        qs.append(quads[Q])
+        probs.append(rsl.make_problem(kind="bjorken", tau_mode="etas", tau_aw0=5 * 0.1973269804 * es / 0.25))
+        dts.append(1e-3)
+    A = rsl.Batch(qs, probs, dts)
+    B = rsl.Batch(qs, probs, dts)
+    A.set_path(0)
+    B.set_path(1)
+    sizes = B.groups()
+    assert sum(sizes) == len(probs) and all(1 <= n <= 16 for n in sizes)
+    assert {(3 * n + 15) // 16 for n in sizes} == {1, 2, 3}
+    A.init()
+    B.init()
+    A.step(30)
+    B.step(30)
+    a = torch.cat([A.f(i).reshape(-1) for i in range(len(probs))]).cpu().numpy()
+    b = torch.cat([B.f(i).reshape(-1) for i in range(len(probs))]).cpu().numpy()
+    amax = torch.stack([A.f(i).abs().max() for i in range(len(probs))]).cpu().numpy()
+    scale = np.repeat(amax, [q.V for q in qs])
+    assert np.max(np.abs(a - b) / scale) < 1e-12
+    assert B.status()[0] == 0
+
+
 def test_bjorken_matrix_cores_vs_oracle(rsl):
     import oracle
     qs, probs, dts = _bj_ensemble(rsl, 5, seed=8, Qs=(40, 101))
