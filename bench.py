@@ -113,11 +113,12 @@ def measured_traffic(dtype, variants):
 
 
 def kernel_forms(variants):
-    """Per class: 's' for the two-kernel form (its HBM traffic does not depend on
-    the velocity slicing), else the fused variant id; '-' for an empty class."""
+    """Per class: 's' for the two-kernel form, 'l' for the loop form (their HBM
+    traffic does not depend on the launch shape), else the fused variant id;
+    '-' for an empty class."""
     from paper_1612_01287_amd import rsl
     shapes = rsl.stage_variants()
-    return ",".join("-" if v < 0 else ("s" if shapes[v][4] else str(v)) for v in variants)
+    return ",".join("-" if v < 0 else {1: "s", 2: "l"}.get(shapes[v][5], str(v)) for v in variants)
 
 
 def kernel_roofline(torch, B, dtype, updates_per_step, variants, chunk, stream, reps=10):

@@ -217,30 +217,39 @@ int rsl_batch_set_path(rsl_batch* b, int path);
  * and finishes sooner.  RSL_EINVAL for a NULL batch or ngroups, or cap < 0. */
 int rsl_batch_groups(const rsl_batch* b, int* ngroups, int* sizes, int cap);
 /* Stage-kernel variants.  One Sod RK3 stage (Sec. III F-G: moments, Landau
- * frame, f^eq, AW relaxation, WENO5 fluxes, RK combination) runs either as
- * one fused kernel per tile of cells or in a two-kernel form (a per-cell
- * kernel for the moments and equilibrium coefficients, then a kernel per
- * (cell, velocity) for fluxes, relaxation and the RK combination).  The fused
- * kernel has launch shapes of W waves per workgroup, NV velocities per lane
- * and 64/TW velocity slots per wave of TW lanes (tiles of TW - 1 cells) and
- * covers V <= W (64/TW) NV; the two-kernel form takes any V (up to 65536),
- * its stream kernel W waves of NV velocities each and its cell kernel
- * cell_waves waves per 63 cells.  Variants differ only in the order of
- * the per-cell moment sums, so results agree to rounding.
+ * frame, f^eq, AW relaxation, WENO5 fluxes, RK combination) runs in one of
+ * three forms (*form): 0, one fused kernel per tile of cells; 1, a two-kernel
+ * form (a per-cell kernel for the moments and equilibrium coefficients, then
+ * a kernel per (cell, velocity slice) for fluxes, relaxation and the RK
+ * combination); 2, a loop form (one workgroup per tile walks all velocities
+ * and, from the output it writes, computes the next stage's coefficients;
+ * the per-cell kernel runs only before the first stage of a call).  The
+ * fused kernel has launch shapes of W waves per workgroup, NV velocities per
+ * lane and 64/TW velocity slots per wave of TW lanes (tiles of TW - 1 cells)
+ * and covers V <= W (64/TW) NV; the other two take any V (up to 65536) with W
+ * waves of NV velocities at a time, and cell_waves waves per 64 cells in the
+ * per-cell kernel.  Variants differ only in the order of the per-cell moment
+ * sums, so results agree to rounding.
  * rsl_stage_variant returns the shape of variant id var, *max_v its largest
- * V and *cell_waves the waves of the two-kernel form's cell kernel (0 for the
- * fused kernel); RSL_EINVAL past the last id.
+ * V, *cell_waves the per-cell kernel's waves (0 for the fused kernel) and
+ * *form its form (each pointer may be NULL); RSL_EINVAL past the last id.
  * A Sod batch sorts its instances into seven classes by V (V <= 32, 64, 128,
- * 256, 320, 384 and V > 384); rsl_batch_variant reports a class's variant (-1
- * if the class is empty) and its largest V; rsl_batch_set_variant selects one
- * (var < 0: the default; RSL_EINVAL if it holds fewer than the class's
- * largest V).  rsl_batch_autotune times every variant that fits each class on
- * stage 2 (reps launches each, after one stage-1 launch; f is left
+ * 256, 320, 384 and V > 384), each launched on a stream of its own;
+ * rsl_batch_variant reports a class's variant (-1 if the class is empty) and
+ * its largest V; rsl_batch_set_variant selects one (var < 0: the default;
+ * RSL_EINVAL if it holds fewer than the class's largest V).  Class index 7
+ * stands for every instance at once: setting a variant there runs the whole
+ * batch as one class (one launch per kernel and stage, on the caller's
+ * stream), var < 0 returns to the seven classes; rsl_batch_variant(b, 7)
+ * reports -1 unless the batch runs that way.  rsl_batch_autotune times every variant that fits each class on
+ * stage 2 as it runs inside a multi-step call (reps launches each, after one
+ * stage-1 launch; f is left
  * unchanged, the work buffer's stage fields are overwritten), keeps the
  * fastest and writes the chosen ids to chosen[7] (if not NULL; -1 for empty
  * classes).  It synchronises the stream.  Changing a variant drops the
  * captured graph. */
-int rsl_stage_variant(int var, int* waves, int* vel_per_slot, int* lanes_per_vel, int* max_v, int* cell_waves);
+int rsl_stage_variant(int var, int* waves, int* vel_per_slot, int* lanes_per_vel, int* max_v, int* cell_waves,
+                      int* form);
 int rsl_batch_variant(const rsl_batch* b, int cls, int* var, int* max_v);
 int rsl_batch_set_variant(rsl_batch* b, int cls, int var);
 int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void* hip_stream, int* chosen);

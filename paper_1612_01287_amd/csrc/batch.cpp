@@ -47,6 +47,7 @@ struct rsl_batch {
     int bj_path = -1;             // -1 automatic, 0 per-instance kernel, 1 matrix cores
     int ql_first[5] = {}, ql_count[5] = {};   // groups of each Q_L (1..4)
     std::vector<int> group_sizes;             // live instances per group, launch order
+    bool merged = false;                      // Sod: every instance in one class (launch.all)
 };
 
 namespace rsl {
@@ -62,7 +63,7 @@ std::vector<int2> schedule(const rsl_batch* b, int cls, int tc) {
     const int X = 8;
     std::vector<int> order;
     for (int i = 0; i < b->n; ++i)
-        if (stage_class_of(b->quads[i]->V) == cls) order.push_back(i);
+        if (cls < 0 || stage_class_of(b->quads[i]->V) == cls) order.push_back(i);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int c) { return b->quads[a]->V > b->quads[c]->V; });
     std::vector<std::vector<std::pair<double, int2>>> q(X);
@@ -221,7 +222,7 @@ void use_variant(StageClass& cl, int var) {
 }
 
 int batch_upload(rsl_batch* b) {
-    std::vector<std::vector<int2>> items(3 * kClasses);
+    std::vector<std::vector<int2>> items(3 * (kClasses + 1));
     size_t total = 0;
     std::vector<int> groups;
     if (b->kind == RSL_BJORKEN) {
@@ -249,9 +250,9 @@ int batch_upload(rsl_batch* b) {
         }
     }
     if (b->kind == RSL_SOD)
-        for (int c = 0; c < kClasses; ++c)
+        for (int c = 0; c <= kClasses; ++c)          // c = kClasses: every instance
             for (int t = 0; t < 3; ++t) {
-                items[3 * c + t] = schedule(b, c, kTileWidths[t]);
+                items[3 * c + t] = schedule(b, c < kClasses ? c : -1, kTileWidths[t]);
                 total += align_up(sizeof(int2) * items[3 * c + t].size(), 256);
             }
     const size_t dbytes = align_up(sizeof(InstDesc) * b->n, 256);
@@ -260,12 +261,13 @@ int batch_upload(rsl_batch* b) {
     rc = hip_check(hipMemcpy(b->dmem, b->host_desc.data(), sizeof(InstDesc) * b->n, hipMemcpyHostToDevice),
                    "hipMemcpy(batch descriptors)");
     size_t off = dbytes;
-    for (int c = 0; c < kClasses && rc == RSL_OK; ++c) {
-        StageClass& cl = b->launch.cl[c];
+    for (int c = 0; c <= kClasses && rc == RSL_OK; ++c) {
+        StageClass& cl = c < kClasses ? b->launch.cl[c] : b->launch.all;
         cl.descs = (const InstDesc*)b->dmem;
         cl.maxV = 0;
         for (int i = 0; i < b->n; ++i)
-            if (b->kind == RSL_SOD && stage_class_of(b->quads[i]->V) == c) cl.maxV = std::max(cl.maxV, b->quads[i]->V);
+            if (b->kind == RSL_SOD && (c == kClasses || stage_class_of(b->quads[i]->V) == c))
+                cl.maxV = std::max(cl.maxV, b->quads[i]->V);
         for (int t = 0; t < 3 && rc == RSL_OK; ++t) {
             const std::vector<int2>& it = items[3 * c + t];
             cl.items_tw[t] = (const int2*)((char*)b->dmem + off);
@@ -275,7 +277,7 @@ int batch_upload(rsl_batch* b) {
                                          hipMemcpyHostToDevice), "hipMemcpy(batch items)");
             off += align_up(sizeof(int2) * it.size(), 256);
         }
-        use_variant(cl, stage_default_variant(c));
+        use_variant(cl, stage_default_variant(c < kClasses ? c : kClasses - 1));
     }
     if (rc == RSL_OK && !groups.empty()) {
         b->groups = (int*)((char*)b->dmem + off);
@@ -300,17 +302,18 @@ int batch_streams(rsl_batch* b) {
 // launches (forked from and joined back into the caller's stream), so that
 // small classes do not leave the GPU idle behind each other.
 int batch_stage_all(rsl_batch* b, int stage, char* f, char* w, hipStream_t s) {
+    if (b->merged) return launch_sod_class_stage(b->launch.all, b->dtype, stage, f, w, s, true);
     int used[kClasses], nu = 0;
     for (int c = 0; c < kClasses; ++c)
         if (b->launch.cl[c].nitems) used[nu++] = c;
-    if (nu <= 1) return nu ? launch_sod_class_stage(b->launch.cl[used[0]], b->dtype, stage, f, w, s) : RSL_OK;
+    if (nu <= 1) return nu ? launch_sod_class_stage(b->launch.cl[used[0]], b->dtype, stage, f, w, s, true) : RSL_OK;
     int rc = batch_streams(b);
     if (rc) return rc;
     if ((rc = hip_check(hipEventRecord(b->ev_fork, s), "hipEventRecord"))) return rc;
     for (int k = 1; k < nu && rc == RSL_OK; ++k)
         rc = hip_check(hipStreamWaitEvent(b->aux[k], b->ev_fork, 0), "hipStreamWaitEvent");
     for (int k = 0; k < nu && rc == RSL_OK; ++k)
-        rc = launch_sod_class_stage(b->launch.cl[used[k]], b->dtype, stage, f, w, k ? b->aux[k] : s);
+        rc = launch_sod_class_stage(b->launch.cl[used[k]], b->dtype, stage, f, w, k ? b->aux[k] : s, true);
     for (int k = 1; k < nu && rc == RSL_OK; ++k) {
         rc = hip_check(hipEventRecord(b->ev_join[k], b->aux[k]), "hipEventRecord");
         if (rc == RSL_OK) rc = hip_check(hipStreamWaitEvent(s, b->ev_join[k], 0), "hipStreamWaitEvent");
@@ -324,6 +327,13 @@ int batch_stage_all(rsl_batch* b, int stage, char* f, char* w, hipStream_t s) {
 // cross-stream wait between stages, and one class's per-cell kernel overlaps
 // another class's stream kernel.
 int batch_sod_steps(rsl_batch* b, char* f, char* w, int nsteps, hipStream_t s) {
+    if (b->merged) {
+        int rc = RSL_OK;
+        for (int it = 0; it < nsteps && rc == RSL_OK; ++it)
+            for (int st = 1; st <= 3 && rc == RSL_OK; ++st)
+                rc = launch_sod_class_stage(b->launch.all, b->dtype, st, f, w, s, it == 0 && st == 1);
+        return rc;
+    }
     int used[kClasses], nu = 0;
     for (int c = 0; c < kClasses; ++c)
         if (b->launch.cl[c].nitems) used[nu++] = c;
@@ -337,7 +347,8 @@ int batch_sod_steps(rsl_batch* b, char* f, char* w, int nsteps, hipStream_t s) {
     for (int k = 0; k < nu && rc == RSL_OK; ++k)
         for (int it = 0; it < nsteps && rc == RSL_OK; ++it)
             for (int st = 1; st <= 3 && rc == RSL_OK; ++st)
-                rc = launch_sod_class_stage(b->launch.cl[used[k]], b->dtype, st, f, w, k ? b->aux[k] : s);
+                rc = launch_sod_class_stage(b->launch.cl[used[k]], b->dtype, st, f, w, k ? b->aux[k] : s,
+                                            it == 0 && st == 1);
     if (nu > 1)
         for (int k = 1; k < nu && rc == RSL_OK; ++k) {
             rc = hip_check(hipEventRecord(b->ev_join[k], b->aux[k]), "hipEventRecord");
@@ -555,11 +566,12 @@ int rsl_batch_groups(const rsl_batch* b, int* ngroups, int* sizes, int cap) {
     return RSL_OK;
 }
 
-int rsl_stage_variant(int var, int* waves, int* vel_per_slot, int* lanes_per_vel, int* max_v, int* cell_waves) {
-    int W, NV, TW, WC;
-    bool split;
-    if (!stage_variant_shape(var, &W, &NV, &TW, &split, &WC))
+int rsl_stage_variant(int var, int* waves, int* vel_per_slot, int* lanes_per_vel, int* max_v, int* cell_waves,
+                      int* form) {
+    int W, NV, TW, WC, fm;
+    if (!stage_variant_shape(var, &W, &NV, &TW, &fm, &WC))
         return set_error(RSL_EINVAL, "unknown stage kernel variant");
+    if (form) *form = fm;
     if (waves) *waves = W;
     if (vel_per_slot) *vel_per_slot = NV;
     if (lanes_per_vel) *lanes_per_vel = TW;
@@ -569,22 +581,28 @@ int rsl_stage_variant(int var, int* waves, int* vel_per_slot, int* lanes_per_vel
 }
 
 int rsl_batch_variant(const rsl_batch* b, int cls, int* var, int* max_v) {
-    if (!b || cls < 0 || cls >= kClasses) return set_error(RSL_EINVAL, "bad batch class");
-    const StageClass& cl = b->launch.cl[cls];
-    if (var) *var = cl.nitems ? cl.var : -1;
+    if (!b || cls < 0 || cls > kClasses) return set_error(RSL_EINVAL, "bad batch class");
+    const StageClass& cl = cls < kClasses ? b->launch.cl[cls] : b->launch.all;
+    if (var) *var = cl.nitems && (cls < kClasses || b->merged) ? cl.var : -1;
     if (max_v) *max_v = cl.maxV;
     return RSL_OK;
 }
 
 int rsl_batch_set_variant(rsl_batch* b, int cls, int var) {
-    if (!b || cls < 0 || cls >= kClasses) return set_error(RSL_EINVAL, "bad batch class");
+    if (!b || cls < 0 || cls > kClasses) return set_error(RSL_EINVAL, "bad batch class");
     if (b->kind != RSL_SOD) return set_error(RSL_EINVAL, "kernel variants exist for Sod batches only");
-    StageClass& cl = b->launch.cl[cls];
+    if (cls == kClasses && var < 0) {
+        b->merged = false;
+        batch_drop_graph(b);
+        return RSL_OK;
+    }
+    StageClass& cl = cls < kClasses ? b->launch.cl[cls] : b->launch.all;
     if (var < 0) var = stage_default_variant(cls);
     const int cap = stage_variant_capacity(var);
     if (cap == 0) return set_error(RSL_EINVAL, "unknown stage kernel variant");
     if (cap < cl.maxV) return set_error(RSL_EINVAL, "variant holds fewer velocities than the class needs");
     use_variant(cl, var);
+    if (cls == kClasses) b->merged = true;
     batch_drop_graph(b);
     return RSL_OK;
 }
@@ -606,15 +624,18 @@ int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void
         // stage 1 once, so that stage 2 (which reads f and f^(1) and writes
         // only f^(2) and the status word) can be repeated on valid data
         use_variant(cl, stage_default_variant(c));
-        rc = launch_sod_class_stage(cl, b->dtype, 1, f, w, s);
+        rc = launch_sod_class_stage(cl, b->dtype, 1, f, w, s, true);
         int best = cl.var;
         float best_ms = 1e30f;
         for (int v = 0; rc == RSL_OK && stage_variant_capacity(v) > 0; ++v) {
             if (stage_variant_capacity(v) < cl.maxV) continue;
             use_variant(cl, v);
-            rc = launch_sod_class_stage(cl, b->dtype, 2, f, w, s);
+            // (the loop form's stage 2 reads the coefficients a previous stage
+            // left; their values do not change the work, so the timing holds)
+            rc = launch_sod_class_stage(cl, b->dtype, 2, f, w, s, false);
             if (rc == RSL_OK) rc = hip_check(hipEventRecord(e0, s), "hipEventRecord");
-            for (int r = 0; r < reps && rc == RSL_OK; ++r) rc = launch_sod_class_stage(cl, b->dtype, 2, f, w, s);
+            for (int r = 0; r < reps && rc == RSL_OK; ++r)
+                rc = launch_sod_class_stage(cl, b->dtype, 2, f, w, s, false);
             if (rc == RSL_OK) rc = hip_check(hipEventRecord(e1, s), "hipEventRecord");
             if (rc == RSL_OK) rc = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
             float ms = 0.0f;

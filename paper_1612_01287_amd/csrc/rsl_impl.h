@@ -111,6 +111,7 @@ constexpr int kClasses = 7;
 constexpr int kMaxVelocities = 1 << 16;
 struct BatchLaunch {
     StageClass cl[kClasses];
+    StageClass all;          // every instance in one class (one launch per kernel and stage)
 };
 
 }  // namespace rsl
@@ -145,12 +146,17 @@ int check_stability(const rsl_quad* q, const rsl_problem* p, double dt);
 int launch_boundary_states(const InstDesc& d, double nL, double TL, double nR, double TR,
                            hipStream_t s);
 int launch_sod_init(const InstDesc& d, hipStream_t s);
-int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s);
+// `fresh`: the stage is the first of a call (the loop form then computes the
+// stage field's coefficients first; the other forms always do).
+int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s, bool fresh);
 int launch_sod_moments(const InstDesc& d, const void* f, double* out, hipStream_t s);
-int launch_sod_class_stage(const StageClass& cl, int dtype, int stage, char* fbase, char* wbase, hipStream_t s);
+int launch_sod_class_stage(const StageClass& cl, int dtype, int stage, char* fbase, char* wbase, hipStream_t s,
+                           bool fresh);
 int stage_class_of(int V);
 int stage_default_variant(int cls);
-bool stage_variant_shape(int var, int* W, int* NV, int* TW, bool* split, int* WC);
+// Stage kernel forms: fused (sod_stage.h), two-kernel and loop (sod_split.h).
+constexpr int kFormFused = 0, kFormSplit = 1, kFormLoop = 2;
+bool stage_variant_shape(int var, int* W, int* NV, int* TW, int* form, int* WC);
 int stage_variant_count();
 int stage_variant_capacity(int var);
 int stage_variant_tile_cells(int var);

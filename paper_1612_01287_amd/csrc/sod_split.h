@@ -40,6 +40,39 @@ struct CellLds {
     double thr[kSeriesTerms];
 };
 
+// The per-cell chain on one wave, from the five moments of the stage field
+// (eq. macro_jk in discrete form): the Landau frame (eqs. E_landau, u_landau),
+// tau (eq. Sod:tau) and the equilibrium coefficients, stored as kCellPar rows
+// of d.cell for cell c when live.  Lanes without a cell carry a rest state so
+// that the series term count stays wave-uniform.
+__device__ __forceinline__ void cell_chain(const InstDesc& d, const double (&M)[5], bool live, int c,
+                                           const double* ser, const double* thr) {
+    CellState cs = landau(M[0], M[1], M[2], M[3], M[4]);
+    if (live && !cs.ok) atomicOr(d.status, 1u);
+    if (!live || !cs.ok) {
+        cs.n = 1.0; cs.T = 1.0; cs.beta = 0.0; cs.gamma = 1.0;
+    }
+    const int nt = series_terms_uniform(wave_max_uniform(cs.beta * cs.beta), thr);
+    double tau = d.tau_r;
+    if (d.tau_mode == RSL_TAU_ETAS) {
+        const double lam = cs.n / (cs.T * cs.T * cs.T);
+        tau = d.tau_aw0 / cs.T * (1.0 - 0.25 * log(lam * d.lambda_ref));
+    }
+    const double it = 1.0 / tau;
+    double c0[kMaxNOm + 1], c1[kMaxNOm + 1];
+    feq_coef(cs.n, cs.T, cs.beta, cs.gamma, d.T0, d.NOm, d.beta_series, ser, nt, c0, c1);
+    if (!live) return;
+    const size_t pitch = (size_t)d.pitch;
+    double* out = d.cell + c;
+    out[0] = cs.gamma * it;
+    out[pitch] = cs.gamma * cs.beta * it;
+#pragma unroll
+    for (int m = 0; m <= kMaxNOm; ++m) {
+        out[(2 + m) * pitch] = c0[m];
+        out[(3 + kMaxNOm + m) * pitch] = c1[m];
+    }
+}
+
 // WC waves split the velocity sum of 64 cells (one lane per cell).
 template <typename Tf, int STAGE, int WC>
 __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, CellLds<WC>& sh) {
@@ -82,8 +115,7 @@ __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, CellLds<W
     red[(w * 5 + 4) * kLanes + lane] = m4;
     __syncthreads();
     if (w != 0) return;
-    // wave 0, all 64 lanes: per-cell coefficients (lanes without a cell carry
-    // a rest state so that the series term count stays wave-uniform)
+    // wave 0, all 64 lanes: per-cell coefficients
     double M[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
@@ -92,29 +124,7 @@ __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, CellLds<W
         for (int ww = 1; ww < W; ++ww) sum += red[(ww * 5 + q) * kLanes + lane];
         M[q] = sum;
     }
-    CellState cs = landau(M[0], M[1], M[2], M[3], M[4]);
-    if (live && !cs.ok) atomicOr(d.status, 1u);
-    if (!live || !cs.ok) {
-        cs.n = 1.0; cs.T = 1.0; cs.beta = 0.0; cs.gamma = 1.0;
-    }
-    const int nt = series_terms_uniform(wave_max_uniform(cs.beta * cs.beta), sh.thr);
-    double tau = d.tau_r;
-    if (d.tau_mode == RSL_TAU_ETAS) {
-        const double lam = cs.n / (cs.T * cs.T * cs.T);
-        tau = d.tau_aw0 / cs.T * (1.0 - 0.25 * log(lam * d.lambda_ref));
-    }
-    const double it = 1.0 / tau;
-    double c0[kMaxNOm + 1], c1[kMaxNOm + 1];
-    feq_coef(cs.n, cs.T, cs.beta, cs.gamma, d.T0, d.NOm, d.beta_series, sh.ser, nt, c0, c1);
-    if (!live) return;
-    double* out = d.cell + c;
-    out[0] = cs.gamma * it;
-    out[pitch] = cs.gamma * cs.beta * it;
-#pragma unroll
-    for (int m = 0; m <= kMaxNOm; ++m) {
-        out[(2 + m) * pitch] = c0[m];
-        out[(3 + kMaxNOm + m) * pitch] = c1[m];
-    }
+    cell_chain(d, M, live, c, sh.ser, sh.thr);
 }
 
 // The W waves of a workgroup share one tile: its cells' coefficients are
@@ -284,6 +294,241 @@ __global__ void __launch_bounds__(W * 64) stream_batch_kernel(const InstDesc* __
     stream_tile<Tf, STAGE, W, NV>(d, it.y, blockIdx.y, (char*)sh.win, sh.cf);
 }
 
+// ---------------------------------------------------------------------------
+// Loop form: one workgroup per 63-cell tile walks the whole velocity set
+// (W waves x NV velocities per round) and, as it writes the stage's output,
+// sums that output's five moments per cell; at the end wave 0 runs the
+// per-cell chain on them and stores the equilibrium coefficients of the NEXT
+// stage over the ones this stage read (each tile reads and writes only its
+// own cells).  The stage field is then read once per stage instead of twice,
+// and the separate per-cell kernel runs only before the first stage of a
+// call, when no previous stage has produced the coefficients.
+template <typename Tf, int W>
+struct LoopLds {
+    union {
+        struct {
+            Tf win[W * kGroup * kWin];
+            double cf[kCellPar * kLanes];
+        } s;
+        double red[W * 5 * kLanes];   // after the velocity loop
+    } u;
+    double ser[kSerLen];
+    double thr[kSeriesTerms];
+};
+
+template <typename Tf, int STAGE, int W, int NV, int K>
+__device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<Tf, W>& sh) {
+    constexpr int G = kGroup;
+    constexpr int WN = kWin;
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    const int z0 = tile * kTileCells;
+    const int c = z0 - 1 + lane;
+    const bool ghost = (c < 0) || (c >= d.nz);
+    const int cc = min(max(c, 0), d.nz - 1);
+    const int hc = lane < 2 ? z0 - 3 + lane : z0 + kLanes - 3 + lane;
+    const bool hghost = (hc < 0) || (hc >= d.nz);
+    const int hcc = min(max(hc, 0), d.nz - 1);
+    const bool eqbc = d.bc == RSL_BC_EQ;
+    const int V = d.V;
+    Tf* win = sh.u.s.win + w * G * WN;       // one window per wave, reused group after group
+    double* cf = sh.u.s.cf;
+
+    const Tf* __restrict__ fcur = (const Tf*)(STAGE == 1 ? d.f : (STAGE == 2 ? d.f1 : d.f2));
+    Tf* __restrict__ fout = (Tf*)(STAGE == 1 ? d.f1 : (STAGE == 2 ? d.f2 : d.f));
+    const Tf* __restrict__ fn = (const Tf*)d.f;
+    const size_t pitch = (size_t)d.pitch;
+    const double dt = d.dt, dzi = d.dz_inv;
+    const bool collide = d.tau_mode != RSL_TAU_INF;
+
+    // this stage's coefficients of the tile's cells (lane 0 holds the left
+    // neighbour's cell, which another workgroup updates and rewrites: it reads
+    // the tile's first cell instead, and its result is never stored), and the
+    // tables of the closing per-cell chain
+    double cA = 0.0, cB = 0.0;
+    const double* cfl = cf + lane;
+    if (collide) {
+        const int ccf = lane == 0 ? min(z0, d.nz - 1) : cc;
+        const int nrow = 2 + 2 * (d.NOm + 1);
+        for (int r = w; r < nrow; r += W) {
+            const int row = r < 2 + d.NOm + 1 ? r : r - (2 + d.NOm + 1) + 3 + kMaxNOm;
+            cf[row * kLanes + lane] = d.cell[(size_t)row * pitch + ccf];
+        }
+        for (int e = threadIdx.x; e < kSerLen; e += W * kLanes) sh.ser[e] = d.tab.ser[e];
+        for (int e = threadIdx.x; e < kSeriesTerms; e += W * kLanes) sh.thr[e] = d.tab.thr[e];
+        __syncthreads();
+        cA = cfl[0];
+        cB = cfl[kLanes];
+    }
+
+    const bool out_lane = !ghost && lane >= 1;
+    unsigned bad = 0;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
+    // Rounds of W NV velocities: the loads of rounds r + 1 .. r + K - 1 are
+    // issued before round r is computed, into other register sets (no copies
+    // between them, so nothing waits for the loads in flight).  Loads are
+    // unconditional (indices clamped into the field) so that the compiler's
+    // wait counts stay exact; the halo lanes' second load is, on other lanes,
+    // a repeat of their own cell.
+    constexpr int step = W * NV;
+    const int hcl = lane < 5 ? hcc : cc;
+    auto load_round = [&](int vb, Tf (&a)[NV], Tf (&h)[NV], Tf (&n)[NV]) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int v = min(vb + w + i * W, V - 1);
+            const Tf* row = fcur + (size_t)v * pitch;
+            a[i] = row[cc];
+            h[i] = row[hcl];
+            if (STAGE > 1) n[i] = fn[(size_t)v * pitch + cc];
+        }
+    };
+    auto round = [&](int vbase, const Tf (&ra)[NV], const Tf (&rh)[NV], const Tf (&rn)[NV]) {
+#pragma unroll
+        for (int i0 = 0; i0 < NV; i0 += G) {
+            if (vbase + w + i0 * W >= V) break;
+#pragma unroll
+            for (int i = i0; i < i0 + G && i < NV; ++i) {
+                const int v = vbase + w + i * W;
+                if (v < V) {
+                    double fc = (double)ra[i], h = (double)rh[i];
+                    if (eqbc) {
+                        const double gl = ldc(d.feqL, v), gr = ldc(d.feqR, v);
+                        fc = ghost ? (c < 0 ? gl : gr) : fc;
+                        h = hghost ? (hc < 0 ? gl : gr) : h;
+                    }
+                    Tf* wb = win + (i - i0) * WN;
+                    wb[lane + 2] = (Tf)fc;
+                    if (lane < 2) wb[lane] = (Tf)h;
+                    else if (lane < 5) wb[kLanes + lane] = (Tf)h;
+                }
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int i = i0; i < i0 + G && i < NV; ++i) {
+                const int v = vbase + w + i * W;
+                if (v < V) {
+                    const __attribute__((address_space(4))) double* vr =
+                        (const __attribute__((address_space(4))) double*)d.tab.vrec + (size_t)v * kVrec;
+                    const double x = vr[0];
+                    const Tf* wb = win + (i - i0) * WN;
+                    double sv[6];
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) sv[q] = (double)wb[lane + q];
+                    double F = 0.0;
+                    if (x > 0.0) F = x * weno5(sv[0], sv[1], sv[2], sv[3], sv[4]);
+                    else if (x < 0.0) F = x * weno5(sv[5], sv[4], sv[3], sv[2], sv[1]);
+                    const double Fm = shift_up(F);
+                    double y = (double)(Tf)(sv[2] + dt * (-(F - Fm) * dzi));
+                    if (collide) {
+                        const double l1 = vr[2], wx = vr[3];
+                        double gsum = 0.0;
+#pragma unroll
+                        for (int m = 0; m <= kMaxNOm; ++m)
+                            if (m <= d.NOm)
+                                gsum = fma(vr[4 + m], fma(l1, cfl[(3 + kMaxNOm + m) * kLanes], cfl[(2 + m) * kLanes]),
+                                           gsum);
+                        y += dt * (cA - cB * x) * (wx * gsum - sv[2]);
+                    }
+                    double out;
+                    if (STAGE == 1) out = y;
+                    else if (STAGE == 2) out = 0.75 * (double)rn[i] + 0.25 * y;
+                    else out = fma(kTwoThirds, y, kThird * (double)rn[i]);
+                    if (out_lane) {
+                        const Tf o = (Tf)out;
+                        if (!isfinite((double)o)) bad |= 2u;
+                        fout[(size_t)v * pitch + c] = o;
+                        // moments of the stored output (the next stage's field)
+                        const double fo = (double)o, p = vr[1] * fo;
+                        m0 += fo;
+                        m1 += x * fo;
+                        m2 += p;
+                        m3 += x * p;
+                        m4 += x * x * p;
+                    }
+                }
+            }
+            wave_lds_sync();   // the group's window reads are done before the next group writes
+        }
+    };
+    // a ring of K register sets: round r is computed while rounds r + 1 ..
+    // r + K - 1 are in flight
+    Tf A[K][NV], H[K][NV], N[K][NV];
+#pragma unroll
+    for (int k = 0; k < K - 1; ++k) load_round(k * step, A[k], H[k], N[k]);
+    for (int vbase = 0; vbase < V; vbase += K * step) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int vb = vbase + k * step;
+            if (vb >= V) break;
+            load_round(vb + (K - 1) * step, A[(k + K - 1) % K], H[(k + K - 1) % K], N[(k + K - 1) % K]);
+            round(vb, A[k], H[k], N[k]);
+        }
+    }
+    if (bad) atomicOr(d.status, bad);
+    if (!collide) return;                 // uniform: nobody reaches the barriers below
+    __syncthreads();                      // windows and coefficients are dead: red overlays them
+    double* red = sh.u.red;
+    red[(w * 5 + 0) * kLanes + lane] = m0;
+    red[(w * 5 + 1) * kLanes + lane] = m1;
+    red[(w * 5 + 2) * kLanes + lane] = m2;
+    red[(w * 5 + 3) * kLanes + lane] = m3;
+    red[(w * 5 + 4) * kLanes + lane] = m4;
+    __syncthreads();
+    if (w != 0) return;
+    double M[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        double sum = red[q * kLanes + lane];
+#pragma unroll
+        for (int ww = 1; ww < W; ++ww) sum += red[(ww * 5 + q) * kLanes + lane];
+        M[q] = sum;
+    }
+    cell_chain(d, M, out_lane, c, sh.ser, sh.thr);
+}
+
+template <typename Tf, int STAGE, int W, int NV, int K>
+__global__ void __launch_bounds__(W * 64) loop_single_kernel(InstDesc d, int ntiles) {
+    __shared__ LoopLds<Tf, W> sh;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    loop_tile<Tf, STAGE, W, NV, K>(d, tile, sh);
+}
+
+template <typename Tf, int STAGE, int W, int NV, int K>
+__global__ void __launch_bounds__(W * 64) loop_batch_kernel(const InstDesc* __restrict__ descs,
+                                                           const int2* __restrict__ items, char* fbase,
+                                                           char* wbase) {
+    __shared__ LoopLds<Tf, W> sh;
+    const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;
+    InstDesc d = descs[it.x];
+    rebase(d, fbase, wbase);
+    loop_tile<Tf, STAGE, W, NV, K>(d, it.y, sh);
+}
+
+// The loop kernel, preceded by the per-cell kernel (WC waves, 64-cell tiles)
+// when `fresh`: at the first stage of a call, or whenever the previous stage
+// did not run in this form.
+template <typename Tf, int STAGE, int W, int NV, int WC, int K>
+int launch_loop_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s, bool fresh) {
+    if (d) {
+        const int ntiles = (d->nz + kTileCells - 1) / kTileCells;
+        const int nct = (d->nz + kCellTile - 1) / kCellTile;
+        if (fresh)
+            hipLaunchKernelGGL((cell_single_kernel<Tf, STAGE, WC>), dim3((nct + 7) / 8 * 8), dim3(WC * 64), 0, s, *d,
+                               nct);
+        hipLaunchKernelGGL((loop_single_kernel<Tf, STAGE, W, NV, K>), dim3((ntiles + 7) / 8 * 8), dim3(W * 64), 0, s,
+                           *d, ntiles);
+    } else {
+        if (fresh)
+            hipLaunchKernelGGL((cell_batch_kernel<Tf, STAGE, WC>), dim3(cl->nitems_tw[2]), dim3(WC * 64), 0, s,
+                               cl->descs, cl->items_tw[2], fb, wb);
+        hipLaunchKernelGGL((loop_batch_kernel<Tf, STAGE, W, NV, K>), dim3(cl->nitems), dim3(W * 64), 0, s, cl->descs,
+                           cl->items, fb, wb);
+    }
+    return hip_check(hipGetLastError(), "sod loop-form stage launch");
+}
+
 // Two launches on one stream: the cell kernel (WC waves) over 64-cell tiles,
 // then the stream kernel (W waves of NV velocities) over (63-cell tile,
 // velocity slice).  A batch class sizes the slice dimension by its largest V.
@@ -308,7 +553,7 @@ int launch_split_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, 
 }
 
 template <typename Tf, int STAGE>
-int launch_cls(int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s) {
+int launch_cls(int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s, bool fresh) {
     switch (var) {
 #define RSL_CASE(id, W, NV, TW) \
     case id: return launch_t<Tf, STAGE, W, NV, TW>(d, cl, fb, wb, s);
@@ -318,16 +563,20 @@ int launch_cls(int var, const InstDesc* d, const StageClass* cl, char* fb, char*
     case id: return launch_split_t<Tf, STAGE, W, NV, WC>(d, cl, fb, wb, s);
         RSL_SPLIT_VARIANTS(RSL_CASE)
 #undef RSL_CASE
+#define RSL_CASE(id, W, NV, WC, K) \
+    case id: return launch_loop_t<Tf, STAGE, W, NV, WC, K>(d, cl, fb, wb, s, fresh);
+        RSL_LOOP_VARIANTS(RSL_CASE)
+#undef RSL_CASE
         default: return set_error(RSL_EINVAL, "unknown stage kernel variant");
     }
 }
 
 template <typename Tf>
 int launch_stage_any(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb,
-                     hipStream_t s) {
-    if (stage == 1) return launch_cls<Tf, 1>(var, d, cl, fb, wb, s);
-    if (stage == 2) return launch_cls<Tf, 2>(var, d, cl, fb, wb, s);
-    return launch_cls<Tf, 3>(var, d, cl, fb, wb, s);
+                     hipStream_t s, bool fresh) {
+    if (stage == 1) return launch_cls<Tf, 1>(var, d, cl, fb, wb, s, fresh);
+    if (stage == 2) return launch_cls<Tf, 2>(var, d, cl, fb, wb, s, fresh);
+    return launch_cls<Tf, 3>(var, d, cl, fb, wb, s, fresh);
 }
 
 }  // namespace

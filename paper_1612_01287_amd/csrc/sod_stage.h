@@ -386,10 +386,18 @@ int launch_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStr
 #define RSL_SPLIT_VARIANTS(X) \
     X(10, 4, 2, 8) X(11, 4, 4, 8) X(12, 4, 8, 8) X(13, 4, 2, 16) X(14, 4, 4, 16) X(15, 4, 8, 16) \
     X(16, 8, 2, 16) X(17, 8, 1, 16) X(18, 2, 4, 16)
+// Variants of the loop form (sod_split.h): waves W walking the velocity set
+// NV velocities at a time with K rounds of loads in flight, cell-kernel waves
+// WC for the first stage of a call.
+#define RSL_LOOP_VARIANTS(X) \
+    X(19, 8, 2, 8, 2) X(20, 8, 2, 16, 3) X(21, 16, 1, 16, 3) X(22, 16, 2, 16, 2) X(23, 8, 2, 16, 4) \
+    X(24, 8, 1, 16, 4) X(25, 16, 1, 16, 4)
 
 }  // namespace
 
-int launch_stage_f64(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s);
-int launch_stage_f32(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s);
+int launch_stage_f64(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s,
+                     bool fresh);
+int launch_stage_f32(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s,
+                     bool fresh);
 
 }  // namespace rsl

@@ -212,7 +212,7 @@ _sig("rsl_batch_groups", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctype
 _sig("rsl_batch_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("rsl_batch_status", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)])
 _ip = ctypes.POINTER(ctypes.c_int)
-_sig("rsl_stage_variant", ctypes.c_int, [ctypes.c_int, _ip, _ip, _ip, _ip, _ip])
+_sig("rsl_stage_variant", ctypes.c_int, [ctypes.c_int, _ip, _ip, _ip, _ip, _ip, _ip])
 _sig("rsl_batch_variant", ctypes.c_int, [_vp, ctypes.c_int, _ip, _ip])
 _sig("rsl_batch_set_variant", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int])
 _sig("rsl_batch_autotune", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _ip])
@@ -222,10 +222,11 @@ N_CLASSES = 7
 
 def stage_variants():
     """[(waves, velocities per lane, lanes per velocity, largest V, cell-kernel
-    waves (0: fused form))] of every stage-kernel variant, by id."""
+    waves (0: fused form), form (0 fused, 1 two-kernel, 2 loop))] of every
+    stage-kernel variant, by id."""
     out = []
     while True:
-        r = [ctypes.c_int() for _ in range(5)]
+        r = [ctypes.c_int() for _ in range(6)]
         if _lib.rsl_stage_variant(len(out), *[ctypes.byref(x) for x in r]) != 0:
             return out
         out.append(tuple(x.value for x in r))

@@ -86,14 +86,14 @@ def test_stage_variants_cover_every_class(rsl):
     vs = rsl.stage_variants()
     assert len(vs) >= 7
     fused = []
-    for W, NV, TW, max_v, wc in vs:
-        assert TW in (32, 64) and 1 <= W <= 16 and NV >= 1
-        if wc:
+    for W, NV, TW, max_v, wc, form in vs:
+        assert TW in (32, 64) and 1 <= W <= 16 and NV >= 1 and form in (0, 1, 2)
+        if form:
             assert TW == 64 and max_v >= 8 * 1024 and wc in (4, 8, 16)   # any Q_xi <= 1024 at Q_L <= 8
         else:
-            assert max_v == W * (64 // TW) * NV
+            assert max_v == W * (64 // TW) * NV and wc == 0
             fused.append(max_v)
     for bound in (32, 64, 128, 256, 320, 384):
         assert any(c >= bound for c in fused)
     assert max(fused) == 384
-    assert any(v[4] for v in vs)
+    assert {v[5] for v in vs} == {0, 1, 2}

@@ -126,6 +126,39 @@ def test_every_stage_variant_matches_default(rsl, dtype, tol):
     assert rc == 0 and bad == -1
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_single_class_launches_match_default(rsl, dtype, tol):
+    """Every instance in one class (class index 7: one launch per kernel and
+    stage on the caller's stream), in the two-kernel and the loop form, agrees
+    with the per-class launches to rounding; index -1 goes back to them."""
+    quads, probs, dts = _ragged_all_classes(rsl, dtype)
+    ref = rsl.Batch(quads, probs, dts)
+    ref.init()
+    ref.step(3)
+    torch.cuda.synchronize()
+    want = [ref.f(i).double().cpu().numpy() for i in range(ref.n)]
+    shapes = rsl.stage_variants()
+    B = rsl.Batch(quads, probs, dts)
+    assert B.variant(7)[0] == -1
+    for form in (1, 2):
+        v = next(k for k, sh in enumerate(shapes) if sh[5] == form)
+        B.set_variant(7, v)
+        assert B.variant(7)[0] == v
+        B.init()
+        B.step(3)
+        torch.cuda.synchronize()
+        for i in range(B.n):
+            got = B.f(i).double().cpu().numpy()
+            assert np.max(np.abs(got - want[i])) / np.max(np.abs(want[i])) < tol, (v, i)
+    B.set_variant(7, -1)
+    assert B.variant(7)[0] == -1
+    B.init()
+    B.step(3)
+    for i in range(B.n):
+        assert torch.equal(B.f(i).double().cpu(), torch.from_numpy(want[i]))
+    assert B.status()[0] == 0
+
+
 def test_set_variant_rejects_small_variants(rsl):
     quads, probs, dts = _ragged_all_classes(rsl, "f64")
     B = rsl.Batch(quads, probs, dts)
