@@ -61,7 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default stage-kernel variants")
     ap.add_argument("--variants", default=None,
-                    help="comma-separated stage-kernel variant per velocity class (-1: empty); skips the autotuner")
+                    help="comma-separated stage-kernel variant per velocity class (-1: empty), and an eighth "
+                         "for the whole batch as one class (-1: per class); skips the autotuner")
     ap.add_argument("--aux", default="all", choices=("none", "all", "bjorken", "ensemble", "learned"),
                     help="also measure the Bjorken batch, the uneven Sod ensemble and the learned correction "
                          "(all), or one of them")
@@ -115,10 +116,14 @@ def measured_traffic(dtype, variants):
 def kernel_forms(variants):
     """Per class: 's' for the two-kernel form, 'l' for the loop form (their HBM
     traffic does not depend on the launch shape), else the fused variant id;
-    '-' for an empty class."""
+    '-' for an empty class; "all:<form>" when the whole batch runs as one
+    class (an eighth entry >= 0)."""
     from paper_1612_01287_amd import rsl
     shapes = rsl.stage_variants()
-    return ",".join("-" if v < 0 else {1: "s", 2: "l"}.get(shapes[v][5], str(v)) for v in variants)
+    form = lambda v: "-" if v < 0 else {1: "s", 2: "l"}.get(shapes[v][5], str(v))
+    if len(variants) > rsl.N_CLASSES and variants[rsl.N_CLASSES] >= 0:
+        return "all:" + form(variants[rsl.N_CLASSES])
+    return ",".join(form(v) for v in variants[:rsl.N_CLASSES])
 
 
 def kernel_roofline(torch, B, dtype, updates_per_step, variants, chunk, stream, reps=10):
@@ -211,7 +216,7 @@ def ensemble_leg(torch, rsl, stream, n=1024, steps=20, chunk=10, seed=4):
     return {"workload": "1024 uneven Sod instances, N_z log-uniform in [256, 16384], Q_xi in {8,16,32,64}, f32",
             "value": updates / sec, "unit": "updates/s", "ms_per_step": sec / steps * 1e3,
             "f_bytes_per_field": 4 * cellvel,
-            "variants": [B.variant(c)[0] for c in range(rsl.N_CLASSES)],
+            "variants": [B.variant(c)[0] for c in range(rsl.N_CLASSES + 1)],
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4),
                          "kernel": "Sod stage kernels of all classes, 32 B per cell-velocity and step"}}
@@ -285,11 +290,11 @@ def main():
     with torch.cuda.stream(stream):
         if a.variants:
             for c, v in enumerate(int(x) for x in a.variants.split(",")):
-                if v >= 0 and B.variant(c)[0] >= 0:
+                if v >= 0 and (c == rsl.N_CLASSES or B.variant(c)[0] >= 0):
                     B.set_variant(c, v)
         elif not a.no_autotune:
             B.autotune(reps=5, stream=stream)
-        variants = [B.variant(c)[0] for c in range(rsl.N_CLASSES)]
+        variants = [B.variant(c)[0] for c in range(rsl.N_CLASSES + 1)]
         for _ in range(max(1, a.warmup // chunk)):
             B.graph_step(chunk)           # first call captures the graph of `chunk` steps
         torch.cuda.synchronize()

@@ -241,12 +241,15 @@ int rsl_batch_groups(const rsl_batch* b, int* ngroups, int* sizes, int cap);
  * stands for every instance at once: setting a variant there runs the whole
  * batch as one class (one launch per kernel and stage, on the caller's
  * stream), var < 0 returns to the seven classes; rsl_batch_variant(b, 7)
- * reports -1 unless the batch runs that way.  rsl_batch_autotune times every variant that fits each class on
- * stage 2 as it runs inside a multi-step call (reps launches each, after one
- * stage-1 launch; f is left
- * unchanged, the work buffer's stage fields are overwritten), keeps the
- * fastest and writes the chosen ids to chosen[7] (if not NULL; -1 for empty
- * classes).  It synchronises the stream.  Changing a variant drops the
+ * reports -1 unless the batch runs that way.
+ * rsl_batch_autotune times every variant that fits each class on stage 2 as
+ * it runs inside a multi-step call (reps launches each, after one stage-1
+ * launch), keeps the fastest per class and writes the ids to chosen[7] (if not
+ * NULL; -1 for empty classes); it then times stage 2 of the whole batch with
+ * those classes on their streams against the whole batch as one class in
+ * every variant that fits, and keeps the fastest (rsl_batch_variant(b, 7)
+ * tells which).  f is left unchanged, the work buffer's stage fields are
+ * overwritten.  It synchronises the stream.  Changing a variant drops the
  * captured graph. */
 int rsl_stage_variant(int var, int* waves, int* vel_per_slot, int* lanes_per_vel, int* max_v, int* cell_waves,
                       int* form);

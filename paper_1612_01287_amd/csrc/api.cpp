@@ -303,7 +303,7 @@ int rsl_step(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_de
     if (p->problem == RSL_SOD) {
         for (int it = 0; it < nsteps; ++it)
             for (int st = 1; st <= 3; ++st)
-                if ((rc = launch_sod_stage(d, st, s, it == 0 && st == 1))) return rc;
+                if ((rc = launch_sod_stage(d, st, s, 3 * it + st - 1))) return rc;
     } else if (nsteps > 0) {
         if ((rc = launch_bj_steps(d, *t, dt, nsteps, s))) return rc;
     }

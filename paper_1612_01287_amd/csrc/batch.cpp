@@ -301,19 +301,29 @@ int batch_streams(rsl_batch* b) {
 // One RK stage of every Sod instance: the velocity classes run as concurrent
 // launches (forked from and joined back into the caller's stream), so that
 // small classes do not leave the GPU idle behind each other.
-int batch_stage_all(rsl_batch* b, int stage, char* f, char* w, hipStream_t s) {
-    if (b->merged) return launch_sod_class_stage(b->launch.all, b->dtype, stage, f, w, s, true);
+int batch_stage_all(rsl_batch* b, int stage, char* f, char* w, hipStream_t s, int seq, int reps = 1) {
+    int rc = RSL_OK;
+    if (b->merged) {
+        for (int r = 0; r < reps && rc == RSL_OK; ++r)
+            rc = launch_sod_class_stage(b->launch.all, b->dtype, stage, f, w, s, seq);
+        return rc;
+    }
     int used[kClasses], nu = 0;
     for (int c = 0; c < kClasses; ++c)
         if (b->launch.cl[c].nitems) used[nu++] = c;
-    if (nu <= 1) return nu ? launch_sod_class_stage(b->launch.cl[used[0]], b->dtype, stage, f, w, s, true) : RSL_OK;
-    int rc = batch_streams(b);
+    if (nu <= 1) {
+        for (int r = 0; r < reps && rc == RSL_OK && nu; ++r)
+            rc = launch_sod_class_stage(b->launch.cl[used[0]], b->dtype, stage, f, w, s, seq);
+        return rc;
+    }
+    rc = batch_streams(b);
     if (rc) return rc;
     if ((rc = hip_check(hipEventRecord(b->ev_fork, s), "hipEventRecord"))) return rc;
     for (int k = 1; k < nu && rc == RSL_OK; ++k)
         rc = hip_check(hipStreamWaitEvent(b->aux[k], b->ev_fork, 0), "hipStreamWaitEvent");
     for (int k = 0; k < nu && rc == RSL_OK; ++k)
-        rc = launch_sod_class_stage(b->launch.cl[used[k]], b->dtype, stage, f, w, k ? b->aux[k] : s, true);
+        for (int r = 0; r < reps && rc == RSL_OK; ++r)
+            rc = launch_sod_class_stage(b->launch.cl[used[k]], b->dtype, stage, f, w, k ? b->aux[k] : s, seq);
     for (int k = 1; k < nu && rc == RSL_OK; ++k) {
         rc = hip_check(hipEventRecord(b->ev_join[k], b->aux[k]), "hipEventRecord");
         if (rc == RSL_OK) rc = hip_check(hipStreamWaitEvent(s, b->ev_join[k], 0), "hipStreamWaitEvent");
@@ -331,7 +341,7 @@ int batch_sod_steps(rsl_batch* b, char* f, char* w, int nsteps, hipStream_t s) {
         int rc = RSL_OK;
         for (int it = 0; it < nsteps && rc == RSL_OK; ++it)
             for (int st = 1; st <= 3 && rc == RSL_OK; ++st)
-                rc = launch_sod_class_stage(b->launch.all, b->dtype, st, f, w, s, it == 0 && st == 1);
+                rc = launch_sod_class_stage(b->launch.all, b->dtype, st, f, w, s, 3 * it + st - 1);
         return rc;
     }
     int used[kClasses], nu = 0;
@@ -348,7 +358,7 @@ int batch_sod_steps(rsl_batch* b, char* f, char* w, int nsteps, hipStream_t s) {
         for (int it = 0; it < nsteps && rc == RSL_OK; ++it)
             for (int st = 1; st <= 3 && rc == RSL_OK; ++st)
                 rc = launch_sod_class_stage(b->launch.cl[used[k]], b->dtype, st, f, w, k ? b->aux[k] : s,
-                                            it == 0 && st == 1);
+                                            3 * it + st - 1);
     if (nu > 1)
         for (int k = 1; k < nu && rc == RSL_OK; ++k) {
             rc = hip_check(hipEventRecord(b->ev_join[k], b->aux[k]), "hipEventRecord");
@@ -492,7 +502,7 @@ int rsl_batch_stage(rsl_batch* b, void* f_dev, void* work_dev, int stage, void* 
     if (!b || !f_dev || !work_dev) return set_error(RSL_EINVAL, "null argument");
     if (b->kind != RSL_SOD) return set_error(RSL_EINVAL, "single stages exist for Sod batches only");
     if (stage < 1 || stage > 3) return set_error(RSL_EINVAL, "stage must be 1, 2 or 3");
-    return batch_stage_all(b, stage, (char*)f_dev, (char*)work_dev, (hipStream_t)hip_stream);
+    return batch_stage_all(b, stage, (char*)f_dev, (char*)work_dev, (hipStream_t)hip_stream, 0);
 }
 
 int rsl_batch_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream) {
@@ -624,7 +634,7 @@ int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void
         // stage 1 once, so that stage 2 (which reads f and f^(1) and writes
         // only f^(2) and the status word) can be repeated on valid data
         use_variant(cl, stage_default_variant(c));
-        rc = launch_sod_class_stage(cl, b->dtype, 1, f, w, s, true);
+        rc = launch_sod_class_stage(cl, b->dtype, 1, f, w, s, 0);
         int best = cl.var;
         float best_ms = 1e30f;
         for (int v = 0; rc == RSL_OK && stage_variant_capacity(v) > 0; ++v) {
@@ -632,10 +642,10 @@ int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void
             use_variant(cl, v);
             // (the loop form's stage 2 reads the coefficients a previous stage
             // left; their values do not change the work, so the timing holds)
-            rc = launch_sod_class_stage(cl, b->dtype, 2, f, w, s, false);
+            rc = launch_sod_class_stage(cl, b->dtype, 2, f, w, s, 1);
             if (rc == RSL_OK) rc = hip_check(hipEventRecord(e0, s), "hipEventRecord");
             for (int r = 0; r < reps && rc == RSL_OK; ++r)
-                rc = launch_sod_class_stage(cl, b->dtype, 2, f, w, s, false);
+                rc = launch_sod_class_stage(cl, b->dtype, 2, f, w, s, 1);
             if (rc == RSL_OK) rc = hip_check(hipEventRecord(e1, s), "hipEventRecord");
             if (rc == RSL_OK) rc = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
             float ms = 0.0f;
@@ -647,6 +657,64 @@ int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void
         }
         use_variant(cl, best);
         if (chosen) chosen[c] = best;
+    }
+    // then the whole batch: the classes on their streams (one fork and join
+    // around all repetitions, as in a multi-step call) against every instance
+    // in one class, per variant that takes the largest V (stage 2 of every
+    // instance; the classes' stage-1 results above serve as input)
+    // (a longer window than per class, best of two, replayed from a captured
+    // graph as multi-step calls run: the choice spans the whole batch and the
+    // candidates are often within a few per cent)
+    auto time_all = [&](float* ms) {
+        *ms = 1e30f;
+        int r2 = RSL_OK;
+        hipGraphExec_t ge = nullptr;
+        if (s) {
+            if (b->launch.all.nitems && (r2 = batch_streams(b))) return r2;
+            r2 = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            if (r2 == RSL_OK) {
+                const int r3 = batch_stage_all(b, 2, f, w, s, 1, 4 * reps);
+                hipGraph_t g = nullptr;
+                const int r4 = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
+                r2 = r3 != RSL_OK ? r3 : r4;
+                if (r2 == RSL_OK) r2 = hip_check(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+                if (g) (void)hipGraphDestroy(g);
+            }
+        }
+        auto run = [&]() {
+            return ge ? hip_check(hipGraphLaunch(ge, s), "hipGraphLaunch") : batch_stage_all(b, 2, f, w, s, 1, 4 * reps);
+        };
+        if (r2 == RSL_OK) r2 = run();
+        for (int trial = 0; trial < 2 && r2 == RSL_OK; ++trial) {
+            float t = 0.0f;
+            r2 = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+            if (r2 == RSL_OK) r2 = run();
+            if (r2 == RSL_OK) r2 = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+            if (r2 == RSL_OK) r2 = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            if (r2 == RSL_OK) r2 = hip_check(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
+            if (r2 == RSL_OK) *ms = std::min(*ms, t);
+        }
+        if (ge) (void)hipGraphExecDestroy(ge);
+        return r2;
+    };
+    if (rc == RSL_OK && b->launch.all.nitems) {
+        b->merged = false;
+        float best_ms = 1e30f;
+        rc = time_all(&best_ms);
+        int best = -1;
+        for (int v = 0; rc == RSL_OK && stage_variant_capacity(v) > 0; ++v) {
+            if (stage_variant_capacity(v) < b->launch.all.maxV) continue;
+            use_variant(b->launch.all, v);
+            b->merged = true;
+            float ms = 0.0f;
+            rc = time_all(&ms);
+            if (rc == RSL_OK && ms < best_ms) {
+                best_ms = ms;
+                best = v;
+            }
+        }
+        b->merged = best >= 0;
+        if (best >= 0) use_variant(b->launch.all, best);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

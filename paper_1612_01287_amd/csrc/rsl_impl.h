@@ -146,12 +146,12 @@ int check_stability(const rsl_quad* q, const rsl_problem* p, double dt);
 int launch_boundary_states(const InstDesc& d, double nL, double TL, double nR, double TR,
                            hipStream_t s);
 int launch_sod_init(const InstDesc& d, hipStream_t s);
-// `fresh`: the stage is the first of a call (the loop form then computes the
-// stage field's coefficients first; the other forms always do).
-int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s, bool fresh);
+// `seq`: the stage's index within a call (0: the first, where the loop form
+// computes the stage field's coefficients with the per-cell kernel first).
+int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s, int seq);
 int launch_sod_moments(const InstDesc& d, const void* f, double* out, hipStream_t s);
 int launch_sod_class_stage(const StageClass& cl, int dtype, int stage, char* fbase, char* wbase, hipStream_t s,
-                           bool fresh);
+                           int seq);
 int stage_class_of(int V);
 int stage_default_variant(int cls);
 // Stage kernel forms: fused (sod_stage.h), two-kernel and loop (sod_split.h).

@@ -43,10 +43,10 @@ struct CellLds {
 // The per-cell chain on one wave, from the five moments of the stage field
 // (eq. macro_jk in discrete form): the Landau frame (eqs. E_landau, u_landau),
 // tau (eq. Sod:tau) and the equilibrium coefficients, stored as kCellPar rows
-// of d.cell for cell c when live.  Lanes without a cell carry a rest state so
+// (stride apart) at out when live.  Lanes without a cell carry a rest state so
 // that the series term count stays wave-uniform.
-__device__ __forceinline__ void cell_chain(const InstDesc& d, const double (&M)[5], bool live, int c,
-                                           const double* ser, const double* thr) {
+__device__ __forceinline__ void cell_chain(const InstDesc& d, const double (&M)[5], bool live, double* out,
+                                           size_t stride, const double* ser, const double* thr) {
     CellState cs = landau(M[0], M[1], M[2], M[3], M[4]);
     if (live && !cs.ok) atomicOr(d.status, 1u);
     if (!live || !cs.ok) {
@@ -62,14 +62,12 @@ __device__ __forceinline__ void cell_chain(const InstDesc& d, const double (&M)[
     double c0[kMaxNOm + 1], c1[kMaxNOm + 1];
     feq_coef(cs.n, cs.T, cs.beta, cs.gamma, d.T0, d.NOm, d.beta_series, ser, nt, c0, c1);
     if (!live) return;
-    const size_t pitch = (size_t)d.pitch;
-    double* out = d.cell + c;
     out[0] = cs.gamma * it;
-    out[pitch] = cs.gamma * cs.beta * it;
+    out[stride] = cs.gamma * cs.beta * it;
 #pragma unroll
     for (int m = 0; m <= kMaxNOm; ++m) {
-        out[(2 + m) * pitch] = c0[m];
-        out[(3 + kMaxNOm + m) * pitch] = c1[m];
+        out[(2 + m) * stride] = c0[m];
+        out[(3 + kMaxNOm + m) * stride] = c1[m];
     }
 }
 
@@ -124,7 +122,7 @@ __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, CellLds<W
         for (int ww = 1; ww < W; ++ww) sum += red[(ww * 5 + q) * kLanes + lane];
         M[q] = sum;
     }
-    cell_chain(d, M, live, c, sh.ser, sh.thr);
+    cell_chain(d, M, live, d.cell + c, (size_t)d.pitch, sh.ser, sh.thr);
 }
 
 // The W waves of a workgroup share one tile: its cells' coefficients are
@@ -295,14 +293,13 @@ __global__ void __launch_bounds__(W * 64) stream_batch_kernel(const InstDesc* __
 }
 
 // ---------------------------------------------------------------------------
-// Loop form: one workgroup per 63-cell tile walks the whole velocity set
-// (W waves x NV velocities per round) and, as it writes the stage's output,
-// sums that output's five moments per cell; at the end wave 0 runs the
-// per-cell chain on them and stores the equilibrium coefficients of the NEXT
-// stage over the ones this stage read (each tile reads and writes only its
-// own cells).  The stage field is then read once per stage instead of twice,
-// and the separate per-cell kernel runs only before the first stage of a
-// call, when no previous stage has produced the coefficients.
+// Loop form: one workgroup per 63-cell tile walks the whole velocity set (W
+// waves x NV velocities per round, K rounds of loads in flight) and, as it
+// writes the stage's output, sums that output's five moments per cell; at the
+// end wave 0 runs the per-cell chain on the sums and stores the NEXT stage's
+// coefficients over the ones this stage read (each tile reads and writes only
+// its own cells).  The stage field is then read once per stage instead of
+// twice, and the per-cell kernel runs only before the first stage of a call.
 template <typename Tf, int W>
 struct LoopLds {
     union {
@@ -310,7 +307,7 @@ struct LoopLds {
             Tf win[W * kGroup * kWin];
             double cf[kCellPar * kLanes];
         } s;
-        double red[W * 5 * kLanes];   // after the velocity loop
+        double red[W * 5 * kLanes];   // moment sums of the waves (outside the velocity walk)
     } u;
     double ser[kSerLen];
     double thr[kSeriesTerms];
@@ -320,6 +317,8 @@ template <typename Tf, int STAGE, int W, int NV, int K>
 __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<Tf, W>& sh) {
     constexpr int G = kGroup;
     constexpr int WN = kWin;
+    constexpr int step = W * NV;
+    const int V = d.V;
     const int lane = threadIdx.x & (kLanes - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     const int z0 = tile * kTileCells;
@@ -330,7 +329,6 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
     const bool hghost = (hc < 0) || (hc >= d.nz);
     const int hcc = min(max(hc, 0), d.nz - 1);
     const bool eqbc = d.bc == RSL_BC_EQ;
-    const int V = d.V;
     Tf* win = sh.u.s.win + w * G * WN;       // one window per wave, reused group after group
     double* cf = sh.u.s.cf;
 
@@ -340,11 +338,12 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
     const size_t pitch = (size_t)d.pitch;
     const double dt = d.dt, dzi = d.dz_inv;
     const bool collide = d.tau_mode != RSL_TAU_INF;
+    const bool out_lane = !ghost && lane >= 1;   // the tile's cells (lane 0: the left neighbour's)
 
-    // this stage's coefficients of the tile's cells (lane 0 holds the left
-    // neighbour's cell, which another workgroup updates and rewrites: it reads
-    // the tile's first cell instead, and its result is never stored), and the
-    // tables of the closing per-cell chain
+    // this stage's coefficients of the tile's cells (written by the previous
+    // stage's workgroup of this tile; lane 0 reads the tile's first cell
+    // instead of its neighbour's, which another workgroup rewrites, and its
+    // result is never stored), and the tables of the closing per-cell chain
     double cA = 0.0, cB = 0.0;
     const double* cfl = cf + lane;
     if (collide) {
@@ -361,7 +360,6 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
         cB = cfl[kLanes];
     }
 
-    const bool out_lane = !ghost && lane >= 1;
     unsigned bad = 0;
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
     // Rounds of W NV velocities: the loads of rounds r + 1 .. r + K - 1 are
@@ -370,7 +368,6 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
     // unconditional (indices clamped into the field) so that the compiler's
     // wait counts stay exact; the halo lanes' second load is, on other lanes,
     // a repeat of their own cell.
-    constexpr int step = W * NV;
     const int hcl = lane < 5 ? hcc : cc;
     auto load_round = [&](int vb, Tf (&a)[NV], Tf (&h)[NV], Tf (&n)[NV]) {
 #pragma unroll
@@ -483,7 +480,7 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
         for (int ww = 1; ww < W; ++ww) sum += red[(ww * 5 + q) * kLanes + lane];
         M[q] = sum;
     }
-    cell_chain(d, M, out_lane, c, sh.ser, sh.thr);
+    cell_chain(d, M, out_lane, d.cell + c, pitch, sh.ser, sh.thr);
 }
 
 template <typename Tf, int STAGE, int W, int NV, int K>
@@ -507,24 +504,23 @@ __global__ void __launch_bounds__(W * 64) loop_batch_kernel(const InstDesc* __re
 }
 
 // The loop kernel, preceded by the per-cell kernel (WC waves, 64-cell tiles)
-// when `fresh`: at the first stage of a call, or whenever the previous stage
-// did not run in this form.
+// at the first stage of a call (seq == 0).
 template <typename Tf, int STAGE, int W, int NV, int WC, int K>
-int launch_loop_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s, bool fresh) {
+int launch_loop_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s, int seq) {
     if (d) {
         const int ntiles = (d->nz + kTileCells - 1) / kTileCells;
         const int nct = (d->nz + kCellTile - 1) / kCellTile;
-        if (fresh)
+        if (seq == 0)
             hipLaunchKernelGGL((cell_single_kernel<Tf, STAGE, WC>), dim3((nct + 7) / 8 * 8), dim3(WC * 64), 0, s, *d,
                                nct);
-        hipLaunchKernelGGL((loop_single_kernel<Tf, STAGE, W, NV, K>), dim3((ntiles + 7) / 8 * 8), dim3(W * 64), 0, s,
-                           *d, ntiles);
+        hipLaunchKernelGGL((loop_single_kernel<Tf, STAGE, W, NV, K>), dim3((ntiles + 7) / 8 * 8), dim3(W * 64), 0,
+                           s, *d, ntiles);
     } else {
-        if (fresh)
+        if (seq == 0)
             hipLaunchKernelGGL((cell_batch_kernel<Tf, STAGE, WC>), dim3(cl->nitems_tw[2]), dim3(WC * 64), 0, s,
                                cl->descs, cl->items_tw[2], fb, wb);
-        hipLaunchKernelGGL((loop_batch_kernel<Tf, STAGE, W, NV, K>), dim3(cl->nitems), dim3(W * 64), 0, s, cl->descs,
-                           cl->items, fb, wb);
+        hipLaunchKernelGGL((loop_batch_kernel<Tf, STAGE, W, NV, K>), dim3(cl->nitems), dim3(W * 64), 0, s,
+                           cl->descs, cl->items, fb, wb);
     }
     return hip_check(hipGetLastError(), "sod loop-form stage launch");
 }
@@ -553,7 +549,7 @@ int launch_split_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, 
 }
 
 template <typename Tf, int STAGE>
-int launch_cls(int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s, bool fresh) {
+int launch_cls(int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s, int seq) {
     switch (var) {
 #define RSL_CASE(id, W, NV, TW) \
     case id: return launch_t<Tf, STAGE, W, NV, TW>(d, cl, fb, wb, s);
@@ -564,7 +560,7 @@ int launch_cls(int var, const InstDesc* d, const StageClass* cl, char* fb, char*
         RSL_SPLIT_VARIANTS(RSL_CASE)
 #undef RSL_CASE
 #define RSL_CASE(id, W, NV, WC, K) \
-    case id: return launch_loop_t<Tf, STAGE, W, NV, WC, K>(d, cl, fb, wb, s, fresh);
+    case id: return launch_loop_t<Tf, STAGE, W, NV, WC, K>(d, cl, fb, wb, s, seq);
         RSL_LOOP_VARIANTS(RSL_CASE)
 #undef RSL_CASE
         default: return set_error(RSL_EINVAL, "unknown stage kernel variant");
@@ -573,10 +569,10 @@ int launch_cls(int var, const InstDesc* d, const StageClass* cl, char* fb, char*
 
 template <typename Tf>
 int launch_stage_any(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb,
-                     hipStream_t s, bool fresh) {
-    if (stage == 1) return launch_cls<Tf, 1>(var, d, cl, fb, wb, s, fresh);
-    if (stage == 2) return launch_cls<Tf, 2>(var, d, cl, fb, wb, s, fresh);
-    return launch_cls<Tf, 3>(var, d, cl, fb, wb, s, fresh);
+                     hipStream_t s, int seq) {
+    if (stage == 1) return launch_cls<Tf, 1>(var, d, cl, fb, wb, s, seq);
+    if (stage == 2) return launch_cls<Tf, 2>(var, d, cl, fb, wb, s, seq);
+    return launch_cls<Tf, 3>(var, d, cl, fb, wb, s, seq);
 }
 
 }  // namespace

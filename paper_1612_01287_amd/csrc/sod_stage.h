@@ -390,14 +390,13 @@ int launch_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStr
 // NV velocities at a time with K rounds of loads in flight, cell-kernel waves
 // WC for the first stage of a call.
 #define RSL_LOOP_VARIANTS(X) \
-    X(19, 8, 2, 8, 2) X(20, 8, 2, 16, 3) X(21, 16, 1, 16, 3) X(22, 16, 2, 16, 2) X(23, 8, 2, 16, 4) \
-    X(24, 8, 1, 16, 4) X(25, 16, 1, 16, 4)
+    X(19, 8, 2, 8, 2) X(20, 8, 1, 8, 4) X(21, 8, 2, 16, 2) X(22, 16, 2, 16, 2)
 
 }  // namespace
 
 int launch_stage_f64(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s,
-                     bool fresh);
+                     int seq);
 int launch_stage_f32(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s,
-                     bool fresh);
+                     int seq);
 
 }  // namespace rsl

@@ -4,8 +4,8 @@
 namespace rsl {
 
 int launch_stage_f32(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s,
-                     bool fresh) {
-    return launch_stage_any<float>(stage, var, d, cl, fb, wb, s, fresh);
+                     int seq) {
+    return launch_stage_any<float>(stage, var, d, cl, fb, wb, s, seq);
 }
 
 }  // namespace rsl

@@ -4,8 +4,8 @@
 namespace rsl {
 
 int launch_stage_f64(int stage, int var, const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s,
-                     bool fresh) {
-    return launch_stage_any<double>(stage, var, d, cl, fb, wb, s, fresh);
+                     int seq) {
+    return launch_stage_any<double>(stage, var, d, cl, fb, wb, s, seq);
 }
 
 bool stage_variant_shape(int var, int* W, int* NV, int* TW, int* form, int* WC) {
@@ -57,19 +57,19 @@ int stage_class_of(int V) {
 
 int stage_default_variant(int cls) { return kDefaultVariant[cls]; }
 
-int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s, bool fresh) {
+int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s, int seq) {
     const int cls = stage_class_of(d.V);
     if (cls < 0) return set_error(RSL_EUNSUPPORTED, "Sod stage: velocity set too large");
     const int var = kDefaultVariant[cls];
-    if (d.dtype == RSL_F64) return launch_stage_f64(stage, var, &d, nullptr, nullptr, nullptr, s, fresh);
-    return launch_stage_f32(stage, var, &d, nullptr, nullptr, nullptr, s, fresh);
+    if (d.dtype == RSL_F64) return launch_stage_f64(stage, var, &d, nullptr, nullptr, nullptr, s, seq);
+    return launch_stage_f32(stage, var, &d, nullptr, nullptr, nullptr, s, seq);
 }
 
 int launch_sod_class_stage(const StageClass& cl, int dtype, int stage, char* fbase, char* wbase, hipStream_t s,
-                           bool fresh) {
+                           int seq) {
     if (cl.nitems == 0) return RSL_OK;
-    if (dtype == RSL_F64) return launch_stage_f64(stage, cl.var, nullptr, &cl, fbase, wbase, s, fresh);
-    return launch_stage_f32(stage, cl.var, nullptr, &cl, fbase, wbase, s, fresh);
+    if (dtype == RSL_F64) return launch_stage_f64(stage, cl.var, nullptr, &cl, fbase, wbase, s, seq);
+    return launch_stage_f32(stage, cl.var, nullptr, &cl, fbase, wbase, s, seq);
 }
 
 }  // namespace rsl
