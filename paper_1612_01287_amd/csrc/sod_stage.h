@@ -390,7 +390,7 @@ int launch_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStr
 // NV velocities at a time with K rounds of loads in flight, cell-kernel waves
 // WC for the first stage of a call.
 #define RSL_LOOP_VARIANTS(X) \
-    X(19, 8, 2, 8, 2) X(20, 8, 1, 8, 4) X(21, 8, 2, 16, 2) X(22, 16, 2, 16, 2)
+    X(19, 8, 2, 8, 2) X(20, 8, 1, 8, 4) X(21, 8, 1, 8, 2) X(22, 8, 1, 8, 3)
 
 }  // namespace
 
