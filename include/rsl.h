@@ -221,9 +221,10 @@ int rsl_batch_groups(const rsl_batch* b, int* ngroups, int* sizes, int cap);
  * three forms (*form): 0, one fused kernel per tile of cells; 1, a two-kernel
  * form (a per-cell kernel for the moments and equilibrium coefficients, then
  * a kernel per (cell, velocity slice) for fluxes, relaxation and the RK
- * combination); 2, a loop form (one workgroup per tile walks all velocities
- * and, from the output it writes, computes the next stage's coefficients;
- * the per-cell kernel runs only before the first stage of a call).  The
+ * combination); 2, a loop form for batches (one workgroup per tile walks
+ * all velocities and, from the output it writes, computes the next stage's
+ * coefficients; the per-cell kernel runs only before the first stage of a
+ * call).  The
  * fused kernel has launch shapes of W waves per workgroup, NV velocities per
  * lane and 64/TW velocity slots per wave of TW lanes (tiles of TW - 1 cells)
  * and covers V <= W (64/TW) NV; the other two take any V (up to 65536) with W

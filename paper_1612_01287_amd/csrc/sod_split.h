@@ -484,14 +484,6 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
 }
 
 template <typename Tf, int STAGE, int W, int NV, int K>
-__global__ void __launch_bounds__(W * 64) loop_single_kernel(InstDesc d, int ntiles) {
-    __shared__ LoopLds<Tf, W> sh;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    loop_tile<Tf, STAGE, W, NV, K>(d, tile, sh);
-}
-
-template <typename Tf, int STAGE, int W, int NV, int K>
 __global__ void __launch_bounds__(W * 64) loop_batch_kernel(const InstDesc* __restrict__ descs,
                                                            const int2* __restrict__ items, char* fbase,
                                                            char* wbase) {
@@ -504,24 +496,16 @@ __global__ void __launch_bounds__(W * 64) loop_batch_kernel(const InstDesc* __re
 }
 
 // The loop kernel, preceded by the per-cell kernel (WC waves, 64-cell tiles)
-// at the first stage of a call (seq == 0).
+// at the first stage of a call (seq == 0).  Batches only: one instance has too
+// few tiles for one workgroup per tile to fill the GPU.
 template <typename Tf, int STAGE, int W, int NV, int WC, int K>
 int launch_loop_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s, int seq) {
-    if (d) {
-        const int ntiles = (d->nz + kTileCells - 1) / kTileCells;
-        const int nct = (d->nz + kCellTile - 1) / kCellTile;
-        if (seq == 0)
-            hipLaunchKernelGGL((cell_single_kernel<Tf, STAGE, WC>), dim3((nct + 7) / 8 * 8), dim3(WC * 64), 0, s, *d,
-                               nct);
-        hipLaunchKernelGGL((loop_single_kernel<Tf, STAGE, W, NV, K>), dim3((ntiles + 7) / 8 * 8), dim3(W * 64), 0,
-                           s, *d, ntiles);
-    } else {
-        if (seq == 0)
-            hipLaunchKernelGGL((cell_batch_kernel<Tf, STAGE, WC>), dim3(cl->nitems_tw[2]), dim3(WC * 64), 0, s,
-                               cl->descs, cl->items_tw[2], fb, wb);
-        hipLaunchKernelGGL((loop_batch_kernel<Tf, STAGE, W, NV, K>), dim3(cl->nitems), dim3(W * 64), 0, s,
-                           cl->descs, cl->items, fb, wb);
-    }
+    if (d) return set_error(RSL_EUNSUPPORTED, "the loop form of the Sod stage runs in batches only");
+    if (seq == 0)
+        hipLaunchKernelGGL((cell_batch_kernel<Tf, STAGE, WC>), dim3(cl->nitems_tw[2]), dim3(WC * 64), 0, s, cl->descs,
+                           cl->items_tw[2], fb, wb);
+    hipLaunchKernelGGL((loop_batch_kernel<Tf, STAGE, W, NV, K>), dim3(cl->nitems), dim3(W * 64), 0, s, cl->descs,
+                       cl->items, fb, wb);
     return hip_check(hipGetLastError(), "sod loop-form stage launch");
 }
 
