@@ -246,12 +246,14 @@ int rsl_batch_groups(const rsl_batch* b, int* ngroups, int* sizes, int cap);
  * rsl_batch_autotune times every variant that fits each class on stage 2 as
  * it runs inside a multi-step call (reps launches each, after one stage-1
  * launch), keeps the fastest per class and writes the ids to chosen[7] (if not
- * NULL; -1 for empty classes); it then times stage 2 of the whole batch with
- * those classes on their streams against the whole batch as one class in
- * every variant that fits, and keeps the fastest (rsl_batch_variant(b, 7)
- * tells which).  f is left unchanged, the work buffer's stage fields are
- * overwritten.  It synchronises the stream.  Changing a variant drops the
- * captured graph. */
+ * NULL; -1 for empty classes); it then times 2 reps whole steps of the
+ * batch (graph-replayed when hip_stream is not the default stream) with those
+ * classes on their streams against the whole batch as one class in every
+ * variant that fits, and keeps the fastest (rsl_batch_variant(b, 7) tells
+ * which).  For those steps it saves f to a temporary device copy (allocated
+ * and freed here) and restores it after: f is left unchanged, the work
+ * buffer's contents are overwritten, the instances' times do not advance.
+ * It synchronises the stream.  Changing a variant drops the captured graph. */
 int rsl_stage_variant(int var, int* waves, int* vel_per_slot, int* lanes_per_vel, int* max_v, int* cell_waves,
                       int* form);
 int rsl_batch_variant(const rsl_batch* b, int cls, int* var, int* max_v);

@@ -299,31 +299,24 @@ int batch_streams(rsl_batch* b) {
 }
 
 // One RK stage of every Sod instance: the velocity classes run as concurrent
-// launches (forked from and joined back into the caller's stream), so that
-// small classes do not leave the GPU idle behind each other.
-int batch_stage_all(rsl_batch* b, int stage, char* f, char* w, hipStream_t s, int seq, int reps = 1) {
+// launches (forked from and joined back into the caller's stream), or the
+// whole batch as one class.
+int batch_stage_all(rsl_batch* b, int stage, char* f, char* w, hipStream_t s, int seq) {
     int rc = RSL_OK;
-    if (b->merged) {
-        for (int r = 0; r < reps && rc == RSL_OK; ++r)
-            rc = launch_sod_class_stage(b->launch.all, b->dtype, stage, f, w, s, seq);
-        return rc;
-    }
+    auto run = [&](const StageClass& cl, hipStream_t st) {
+        return launch_sod_class_stage(cl, b->dtype, stage, f, w, st, seq);
+    };
+    if (b->merged) return run(b->launch.all, s);
     int used[kClasses], nu = 0;
     for (int c = 0; c < kClasses; ++c)
         if (b->launch.cl[c].nitems) used[nu++] = c;
-    if (nu <= 1) {
-        for (int r = 0; r < reps && rc == RSL_OK && nu; ++r)
-            rc = launch_sod_class_stage(b->launch.cl[used[0]], b->dtype, stage, f, w, s, seq);
-        return rc;
-    }
+    if (nu <= 1) return nu ? run(b->launch.cl[used[0]], s) : RSL_OK;
     rc = batch_streams(b);
     if (rc) return rc;
     if ((rc = hip_check(hipEventRecord(b->ev_fork, s), "hipEventRecord"))) return rc;
     for (int k = 1; k < nu && rc == RSL_OK; ++k)
         rc = hip_check(hipStreamWaitEvent(b->aux[k], b->ev_fork, 0), "hipStreamWaitEvent");
-    for (int k = 0; k < nu && rc == RSL_OK; ++k)
-        for (int r = 0; r < reps && rc == RSL_OK; ++r)
-            rc = launch_sod_class_stage(b->launch.cl[used[k]], b->dtype, stage, f, w, k ? b->aux[k] : s, seq);
+    for (int k = 0; k < nu && rc == RSL_OK; ++k) rc = run(b->launch.cl[used[k]], k ? b->aux[k] : s);
     for (int k = 1; k < nu && rc == RSL_OK; ++k) {
         rc = hip_check(hipEventRecord(b->ev_join[k], b->aux[k]), "hipEventRecord");
         if (rc == RSL_OK) rc = hip_check(hipStreamWaitEvent(s, b->ev_join[k], 0), "hipStreamWaitEvent");
@@ -658,22 +651,24 @@ int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void
         use_variant(cl, best);
         if (chosen) chosen[c] = best;
     }
-    // then the whole batch: the classes on their streams (one fork and join
-    // around all repetitions, as in a multi-step call) against every instance
-    // in one class, per variant that takes the largest V (stage 2 of every
-    // instance; the classes' stage-1 results above serve as input)
-    // (a longer window than per class, best of two, replayed from a captured
-    // graph as multi-step calls run: the choice spans the whole batch and the
-    // candidates are often within a few per cent)
+    // then the whole batch: the classes on their streams against every
+    // instance in one class, per variant that takes the largest V, timed on
+    // 2 reps whole steps replayed from a captured graph (as graph_step runs
+    // them), best of two
+    void* fsave = nullptr;
     auto time_all = [&](float* ms) {
         *ms = 1e30f;
         int r2 = RSL_OK;
         hipGraphExec_t ge = nullptr;
+        // every candidate from the same state (the cost of a step depends on it)
+        auto restore = [&]() {
+            return hip_check(hipMemcpyAsync(f, fsave, b->f_bytes, hipMemcpyDeviceToDevice, s), "restore f");
+        };
         if (s) {
             if (b->launch.all.nitems && (r2 = batch_streams(b))) return r2;
             r2 = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
             if (r2 == RSL_OK) {
-                const int r3 = batch_stage_all(b, 2, f, w, s, 1, 4 * reps);
+                const int r3 = batch_sod_steps(b, f, w, 2 * reps, s);
                 hipGraph_t g = nullptr;
                 const int r4 = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
                 r2 = r3 != RSL_OK ? r3 : r4;
@@ -682,12 +677,14 @@ int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void
             }
         }
         auto run = [&]() {
-            return ge ? hip_check(hipGraphLaunch(ge, s), "hipGraphLaunch") : batch_stage_all(b, 2, f, w, s, 1, 4 * reps);
+            return ge ? hip_check(hipGraphLaunch(ge, s), "hipGraphLaunch") : batch_sod_steps(b, f, w, 2 * reps, s);
         };
+        if (r2 == RSL_OK) r2 = restore();
         if (r2 == RSL_OK) r2 = run();
         for (int trial = 0; trial < 2 && r2 == RSL_OK; ++trial) {
             float t = 0.0f;
-            r2 = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+            r2 = restore();
+            if (r2 == RSL_OK) r2 = hip_check(hipEventRecord(e0, s), "hipEventRecord");
             if (r2 == RSL_OK) r2 = run();
             if (r2 == RSL_OK) r2 = hip_check(hipEventRecord(e1, s), "hipEventRecord");
             if (r2 == RSL_OK) r2 = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
@@ -697,7 +694,13 @@ int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void
         if (ge) (void)hipGraphExecDestroy(ge);
         return r2;
     };
-    if (rc == RSL_OK && b->launch.all.nitems) {
+    // (whole steps on the real data: f is saved first and restored after)
+    const bool whole = rc == RSL_OK && b->launch.all.nitems;
+    if (whole) {
+        rc = hip_check(hipMalloc(&fsave, b->f_bytes), "hipMalloc(autotune copy of f)");
+        if (rc == RSL_OK) rc = hip_check(hipMemcpyAsync(fsave, f, b->f_bytes, hipMemcpyDeviceToDevice, s), "copy f");
+    }
+    if (whole && rc == RSL_OK) {
         b->merged = false;
         float best_ms = 1e30f;
         rc = time_all(&best_ms);
@@ -715,6 +718,12 @@ int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void
         }
         b->merged = best >= 0;
         if (best >= 0) use_variant(b->launch.all, best);
+    }
+    if (fsave) {
+        const int rc2 = hip_check(hipMemcpyAsync(f, fsave, b->f_bytes, hipMemcpyDeviceToDevice, s), "restore f");
+        const int rc3 = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        (void)hipFree(fsave);
+        if (rc == RSL_OK) rc = rc2 != RSL_OK ? rc2 : rc3;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
