@@ -291,9 +291,15 @@ int rsl_mlp_to_bf16(const float* params, unsigned short* params_bf16, void* hip_
 int rsl_mlp_forward(const unsigned short* params_bf16, const float* x, int n, float* y, unsigned short* h1,
                     unsigned short* h2, void* hip_stream);
 /* grad[27395] = d/dparams of mean((y - t)^2) over the n x 3 outputs, from the
- * activations of the matching forward call (grad is overwritten). */
+ * activations of the matching forward call (grad is overwritten).  work is a
+ * device buffer of rsl_mlp_backward_work(n) floats owned by the caller
+ * (partial gradients of up to 256 workgroups, added in a fixed order, so the
+ * result does not depend on scheduling); calls that share it must not
+ * overlap.  RSL_EINVAL for NULL pointers or n <= 0. */
+size_t rsl_mlp_backward_work(int n);
 int rsl_mlp_backward(const unsigned short* params_bf16, const float* x, const unsigned short* h1,
-                     const unsigned short* h2, const float* y, const float* t, int n, float* grad, void* hip_stream);
+                     const unsigned short* h2, const float* y, const float* t, int n, float* grad, float* work,
+                     void* hip_stream);
 /* One Adam step (step >= 1, bias-corrected) on the fp32 parameters; refreshes
  * the bf16 copy. */
 int rsl_mlp_adam(float* params, const float* grad, float* m, float* v, unsigned short* params_bf16, int step, float lr,

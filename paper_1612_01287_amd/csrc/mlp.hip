@@ -177,8 +177,10 @@ __global__ void __launch_bounds__(TPB) mlp_forward_kernel(const unsigned short* 
 }
 
 // Backward for loss = mean over n samples and 3 outputs of (y - t)^2.
-// Per tile: dY, dZ2 = (dY W3^T) .* [h2 > 0], dZ1 = (dZ2 W2^T) .* [h1 > 0];
-// weight gradients accumulate into fp32 g with atomics.
+// Per tile: dY, dZ2 = (dY W3^T) .* [h2 > 0], dZ1 = (dZ2 W2^T) .* [h1 > 0].
+// Workgroup b sums the gradient of its tiles (b, b + G, ...) into its own
+// fp32 row part[b][NPARAM] (every entry owned by one lane: no atomics); a
+// second kernel adds the G rows in a fixed order.
 struct BL {
     unsigned short x[ROWS * KI];
     unsigned short h1[ROWS * NH];
@@ -186,21 +188,29 @@ struct BL {
     unsigned short dy[ROWS * OP];
     unsigned short dz2[ROWS * NH];
     unsigned short dz1[ROWS * NH];
+    float dyf[ROWS * OP];          // dY in fp32 (the output bias gradient)
 };
+
+// Workgroups of the backward kernel (rows of partial gradients).
+constexpr int kBwdGroups = 256;
+int bwd_groups(int n) { return std::max(1, std::min(kBwdGroups, (n + ROWS - 1) / ROWS)); }
 
 __global__ void __launch_bounds__(TPB) mlp_backward_kernel(const unsigned short* __restrict__ pb,
                                                            const float* __restrict__ x,
                                                            const unsigned short* __restrict__ h1g,
                                                            const unsigned short* __restrict__ h2g,
                                                            const float* __restrict__ y, const float* __restrict__ t,
-                                                           int n, float* __restrict__ g) {
+                                                           int n, float* __restrict__ part) {
     extern __shared__ char smem[];
     WL& W = *(WL*)smem;
     BL& B = *(BL*)(smem + sizeof(WL));
     load_weights(W, pb);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const float scale = 2.0f / ((float)n * NO);
+    float* __restrict__ g = part + (size_t)blockIdx.x * NPARAM;
     for (int r0 = blockIdx.x * ROWS; r0 < n; r0 += gridDim.x * ROWS) {
+        const bool first = r0 == blockIdx.x * ROWS;     // the row starts from this tile's values
+        auto put = [&](int i, float v) { g[i] = first ? v : g[i] + v; };
         __syncthreads();
         for (int e = threadIdx.x; e < ROWS * KI; e += blockDim.x) {
             const int r = e / KI, c = e - r * KI;
@@ -216,7 +226,7 @@ __global__ void __launch_bounds__(TPB) mlp_backward_kernel(const unsigned short*
             float v = 0.f;
             if (r0 + r < n && c < NO) v = scale * (y[(size_t)(r0 + r) * NO + c] - t[(size_t)(r0 + r) * NO + c]);
             B.dy[e] = to_bf16(v);
-            if (c < NO && v != 0.f) atomicAdd(&g[OFF_B3 + c], v);
+            B.dyf[e] = v;
         }
         __syncthreads();
         const int rw = 16 * w;
@@ -263,18 +273,33 @@ __global__ void __launch_bounds__(TPB) mlp_backward_kernel(const unsigned short*
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * mi + drow(lane, r);
-                if (row < fan_in && col < fan_out && acc[r] != 0.f) atomicAdd(&g[goff + row * ldw + col], acc[r]);
+                if (row < fan_in && col < fan_out) put(goff + row * ldw + col, acc[r]);
             }
         }
-        // bias gradients of the hidden layers
-        for (int c = threadIdx.x; c < 2 * NH; c += blockDim.x) {
-            const unsigned short* dz = c < NH ? B.dz1 : B.dz2;
-            const int cc = c % NH;
+        // bias gradients: hidden layers from the bf16 dZ, the output layer from dY in fp32
+        for (int c = threadIdx.x; c < 2 * NH + NO; c += blockDim.x) {
             float s = 0.f;
-            for (int r = 0; r < ROWS; ++r) s += from_bf16(dz[r * NH + cc]);
-            if (s != 0.f) atomicAdd(&g[(c < NH ? OFF_B1 : OFF_B2) + cc], s);
+            if (c < 2 * NH) {
+                const unsigned short* dz = c < NH ? B.dz1 : B.dz2;
+                const int cc = c % NH;
+                for (int r = 0; r < ROWS; ++r) s += from_bf16(dz[r * NH + cc]);
+                put((c < NH ? OFF_B1 : OFF_B2) + cc, s);
+            } else {
+                const int cc = c - 2 * NH;
+                for (int r = 0; r < ROWS; ++r) s += B.dyf[r * OP + cc];
+                put(OFF_B3 + cc, s);
+            }
         }
     }
+}
+
+// grad[p] = sum over the G partial rows, in row order.
+__global__ void grad_reduce_kernel(const float* __restrict__ part, int G, float* __restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NPARAM) return;
+    float s = 0.f;
+    for (int b = 0; b < G; ++b) s += part[(size_t)b * NPARAM + p];
+    grad[p] = s;
 }
 
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -420,18 +445,23 @@ int rsl_mlp_forward(const unsigned short* params_bf16, const float* x, int n, fl
     return hip_check(hipGetLastError(), "mlp_forward_kernel launch");
 }
 
+size_t rsl_mlp_backward_work(int n) { return n > 0 ? (size_t)bwd_groups(n) * NPARAM : 0; }
+
 int rsl_mlp_backward(const unsigned short* params_bf16, const float* x, const unsigned short* h1,
-                     const unsigned short* h2, const float* y, const float* t, int n, float* grad, void* hip_stream) {
-    if (!params_bf16 || !x || !h1 || !h2 || !y || !t || !grad || n <= 0) return set_error(RSL_EINVAL, "bad argument");
+                     const unsigned short* h2, const float* y, const float* t, int n, float* grad, float* work,
+                     void* hip_stream) {
+    if (!params_bf16 || !x || !h1 || !h2 || !y || !t || !grad || !work || n <= 0)
+        return set_error(RSL_EINVAL, "bad argument");
     static const hipError_t attr = hipFuncSetAttribute((const void*)mlp_backward_kernel,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBwdLds);
     if (attr != hipSuccess) return hip_check(attr, "hipFuncSetAttribute(mlp_backward_kernel)");
     hipStream_t s = (hipStream_t)hip_stream;
-    int rc = hip_check(hipMemsetAsync(grad, 0, sizeof(float) * NPARAM, s), "clear gradient");
+    const int G = bwd_groups(n);
+    hipLaunchKernelGGL(mlp_backward_kernel, dim3(G), dim3(TPB), kBwdLds, s, params_bf16, x, h1, h2, y, t, n, work);
+    int rc = hip_check(hipGetLastError(), "mlp_backward_kernel launch");
     if (rc) return rc;
-    hipLaunchKernelGGL(mlp_backward_kernel, dim3(grid_rows(n)), dim3(TPB), kBwdLds, s, params_bf16, x, h1, h2, y, t, n,
-                       grad);
-    return hip_check(hipGetLastError(), "mlp_backward_kernel launch");
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, s, work, G, grad);
+    return hip_check(hipGetLastError(), "grad_reduce_kernel launch");
 }
 
 int rsl_mlp_adam(float* params, const float* grad, float* m, float* v, unsigned short* params_bf16, int step, float lr,

@@ -126,7 +126,8 @@ def train(X, T, epochs=20, batch=8192, lr=2e-3, seed=0, margin=0.05, init=None, 
     nb = (n + batch - 1) // batch
     for ep in range(epochs):
         perm = torch.randperm(n, generator=g).to(X.device)
-        tot, cnt = 0.0, 0
+        tot = torch.zeros((), dtype=torch.float64, device=X.device)   # summed on the device: no sync per batch
+        cnt = 0
         for s in range(0, n, batch):
             idx = perm[s:s + batch]
             xb, tb = Xs[idx].contiguous(), Ts[idx].contiguous()
@@ -135,9 +136,9 @@ def train(X, T, epochs=20, batch=8192, lr=2e-3, seed=0, margin=0.05, init=None, 
             lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / max(1, epochs * nb)))
             net.adam(lr=lr_t)
             step += 1
-            tot += float(((y - tb) ** 2).mean()) * xb.shape[0]
+            tot += ((y - tb) ** 2).mean().double() * xb.shape[0]
             cnt += xb.shape[0]
-        hist.append(tot / cnt)
+        hist.append(float(tot) / cnt)
     _fold_output_scale(net, tsc)
     span = Xs.max(dim=0).values - Xs.min(dim=0).values
     lo = (Xs.min(dim=0).values - margin * span - 1e-6).contiguous()

@@ -340,7 +340,8 @@ _u16p = ctypes.c_void_p
 _sig("rsl_mlp_features", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, ctypes.c_double, _vp, _vp, _vp, _vp])
 _sig("rsl_mlp_to_bf16", ctypes.c_int, [_vp, _vp, _vp])
 _sig("rsl_mlp_forward", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp])
-_sig("rsl_mlp_backward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp])
+_sig("rsl_mlp_backward", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp])
+_sig("rsl_mlp_backward_work", ctypes.c_size_t, [ctypes.c_int])
 _sig("rsl_mlp_adam", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, ctypes.c_float, _vp])
 _sig("rsl_mlp_tmunu", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp])
@@ -366,6 +367,7 @@ class MLP:
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.grad = torch.zeros_like(self.params)
+        self._work = None                   # backward partial gradients (rsl_mlp_backward_work floats)
         self.step_count = 0
         self.refresh()
 
@@ -383,8 +385,11 @@ class MLP:
         return (y, h1, h2) if keep else y
 
     def backward(self, x, h1, h2, y, t, stream=None):
+        need = _lib.rsl_mlp_backward_work(x.shape[0])
+        if self._work is None or self._work.numel() < need:
+            self._work = torch.empty(need, dtype=torch.float32, device=self.params.device)
         check(_lib.rsl_mlp_backward(_p(self.pb), _p(x), _p(h1), _p(h2), _p(y), _p(t), x.shape[0], _p(self.grad),
-                                    _stream(stream)))
+                                    _p(self._work), _stream(stream)))
         return self.grad
 
     def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
