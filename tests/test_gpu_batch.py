@@ -246,6 +246,39 @@ def test_graph_replay_equals_eager(rsl):
         assert B.time(0) == pytest.approx(12 * dts[0], rel=1e-14)
 
 
+def _loop_variant(rsl):
+    return next(k for k, sh in enumerate(rsl.stage_variants()) if sh[5] == 2)
+
+
+def test_loop_form_graph_and_stages(rsl):
+    """The whole batch as one class in the loop form: graph replays equal eager
+    steps bitwise (each call starts with the per-cell kernel, later stages take
+    the coefficients the previous stage left); single stages (each computing
+    its coefficients afresh) agree with whole steps to rounding."""
+    quads, probs, dts = _sod_ensemble(rsl, "f64", seed=23, n=7)
+    v = _loop_variant(rsl)
+    A, B, C = (rsl.Batch(quads, probs, dts) for _ in range(3))
+    for X in (A, B, C):
+        X.set_variant(7, v)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        A.init()
+        B.init()
+        C.init()
+        for rep in range(3):
+            A.step(4)
+            B.graph_step(4)
+            for _ in range(4):
+                for st in (1, 2, 3):
+                    C.stage(st)
+            torch.cuda.synchronize()
+            for i in range(len(probs)):
+                assert torch.equal(A.f(i), B.f(i)), (rep, i)
+                a, c = A.f(i).cpu().numpy(), C.f(i).cpu().numpy()
+                assert np.max(np.abs(a - c)) / np.max(np.abs(a)) < 1e-12, (rep, i)
+    assert B.status()[0] == 0
+
+
 def _bj_ensemble(rsl, n, seed, dtype="f64", Qs=(20, 37, 64, 200)):
     rng = np.random.default_rng(seed)
     quads = {Q: rsl.Quadrature(3, Q, 4) for Q in Qs}
