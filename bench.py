@@ -226,7 +226,7 @@ def ensemble_leg(torch, rsl, stream, n=1024, steps=20, chunk=10, seed=4):
 def learned_leg(torch, stream):
     from paper_1612_01287_amd import learned
     t0 = time.perf_counter()
-    X, T = learned.generate(n_runs=512, nz=2048, t_snaps=(0.05, 0.1, 0.15, 0.2, 0.25), seed=5, q_lo=8, q_hi=128)
+    X, T = learned.generate(n_runs=1024, nz=2048, t_snaps=(0.05, 0.1, 0.15, 0.2, 0.25), seed=5, q_lo=8, q_hi=128)
     corr, hist = learned.train(X, T, epochs=100, batch=8192, lr=2e-3, seed=1, margin=0.25)
     torch.cuda.synchronize()
     prep = time.perf_counter() - t0
