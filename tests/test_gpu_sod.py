@@ -4,8 +4,9 @@ Bar: max |f_gpu - f_oracle| / max |f_oracle| <= 1e-12 with f stored in FP64,
 <= 1e-5 with f stored in FP32 (the oracle then rounds f to binary32 after each
 RK stage as the kernels do).  Cases cover several tiles and a ragged last tile,
 both ghost-cell rules, the three relaxation-time laws, odd Q_xi (a node at
-xi = 0), velocity sets too large for the LDS window, moving states, and the
-full C2 size (N_z = 4096, R-SLB(4;100), Q_L = 3).
+xi = 0), velocity sets too large for the LDS window, moving states, the
+full C2 size (N_z = 4096, R-SLB(4;100), Q_L = 3), and the whole 16-instance
+sweep at that size in the launch configuration the benchmark times.
 """
 import numpy as np
 import pytest
@@ -166,6 +167,36 @@ def test_c2_full_size(rsl):
     dt = 0.5 / 4096
     inst.step(dt, 2)
     assert _rel(inst.f().cpu().numpy(), S.run(S.init(), dt, 2)) < TOL["f64"]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sweep_full_size_as_one_class(rsl, dtype):
+    """The sweep at full size in the launch configuration the benchmark times:
+    16 instances (N_z = 4096, Q_xi in {8, 16, 40, 100}, eta/s in {0.01, 0.1,
+    1, 10}) as one class in the loop form, 2 steps; the R-SLB(4;100) and
+    R-SLB(3;8)-sized instances at eta/s = 0.01 and 10 against the oracle."""
+    from tests.test_gpu_batch import _loop_variant
+    nz, dt = 4096, 0.5 / 4096
+    QXI, ETAS = (8, 16, 40, 100), (0.01, 0.1, 1.0, 10.0)
+    quads, probs, keys = [], [], []
+    for Q in QXI:
+        q = rsl.Quadrature(3, Q, 4)
+        for es in ETAS:
+            quads.append(q)
+            probs.append(rsl.make_problem(nz=nz, dtype=dtype, bc="outflow", tau_mode="etas", tau_aw0=0.3854 * es,
+                                          **inputs.SOD_C1))
+            keys.append((Q, es))
+    B = rsl.Batch(quads, probs, [dt] * len(probs))
+    B.set_variant(7, _loop_variant(rsl))
+    B.init()
+    B.step(2)
+    assert B.status()[0] == 0
+    for (Q, es) in ((100, 0.01), (100, 10.0), (8, 0.01), (8, 10.0)):
+        i = keys.index((Q, es))
+        S = oracle.Sod(oracle.VelocitySet(3, Q, 4), nz, tau_mode=oracle.TAU_ETAS, tau_aw0=0.3854 * es,
+                       lambda_ref=1.0, bc=oracle.BC_OUTFLOW, store_f32=(dtype == "f32"), **inputs.SOD_C1)
+        ref = S.run(S.init(), dt, 2)
+        assert _rel(B.f(i).double().cpu().numpy(), ref) < TOL[dtype], (Q, es)
 
 
 @pytest.mark.parametrize("QL,Q,NOm,nz", [(3, 8, 3, 130), (3, 16, 4, 257), (3, 64, 4, 100), (3, 128, 4, 90),
