@@ -279,6 +279,33 @@ def test_loop_form_graph_and_stages(rsl):
     assert B.status()[0] == 0
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_loop_form_every_relaxation_law(rsl, dtype, tol):
+    """Constant tau, the eta/s law and free streaming (no collision term: the
+    loop form then skips the coefficients and the closing chain) in one batch
+    as one class, against single-instance steps (two-kernel form)."""
+    cases = [(8, 130, "const"), (16, 70, "etas"), (40, 200, "inf"), (100, 64, "etas"), (8, 5, "inf"),
+             (64, 90, "const")]
+    quads, probs, dts = [], [], []
+    for Q, nz, mode in cases:
+        quads.append(rsl.Quadrature(3, Q, min(Q - 1, 4)))
+        probs.append(rsl.make_problem(nz=nz, dtype=dtype, bc="eq" if nz % 2 else "outflow", tau_mode=mode,
+                                      tau_r=0.02, tau_aw0=0.3854 * 0.5, nL=1.0, TL=1.0, nR=0.4, TR=0.8))
+        dts.append(0.4 / nz)
+    B = rsl.Batch(quads, probs, dts)
+    B.set_variant(7, _loop_variant(rsl))
+    B.init()
+    B.step(6)
+    torch.cuda.synchronize()
+    for i, (q, p) in enumerate(zip(quads, probs)):
+        inst = rsl.Instance(q, p)
+        inst.init()
+        inst.step(dts[i], 6)
+        a, b = inst.f().double().cpu().numpy(), B.f(i).double().cpu().numpy()
+        assert np.max(np.abs(a - b)) / np.max(np.abs(a)) < tol, (i, cases[i])
+    assert B.status()[0] == 0
+
+
 def _bj_ensemble(rsl, n, seed, dtype="f64", Qs=(20, 37, 64, 200)):
     rng = np.random.default_rng(seed)
     quads = {Q: rsl.Quadrature(3, Q, 4) for Q in Qs}
