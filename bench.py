@@ -10,7 +10,10 @@ Metric: distribution updates per second, one update = one (cell, velocity,
 RK stage).
 
 Prints one JSON line (see the repository's measurement contract).  Its "aux"
-object carries three further measurements on seeded synthetic inputs:
+object carries four further measurements on seeded synthetic inputs:
+  c1       the near-inviscid tube (N_z = 400, R-SLB(3;8), tau_r = 1e-3,
+           dt = 1.25e-3, 200 steps), launch-bound: updates/s and the last
+           step against the oracle;
   bjorken  4096 Bjorken runs (T0 log-uniform in [0.5, 2] GeV, eta/s
            log-uniform in [0.01, 10], Q_xi uniform in {20..200}, Q_L = 3,
            ideal gas), a 1000-step window at dtau = 1e-3 in one launch; the
@@ -18,12 +21,14 @@ object carries three further measurements on seeded synthetic inputs:
   ensemble 1024 uneven Sod instances (N_z log-uniform in [256, 16384],
            Q_xi in {8, 16, 32, 64}, T_L/T_R uniform in [1.1, 3], tau_r
            log-uniform in [1e-4, 1], dt = min(0.5/N_z, tau_r/2)), f in
-           binary32, graph replays; 1.4 GB per field, so HBM-bound;
+           binary32, 100 steps in graph replays of 10; 1.4 GB per field,
+           so HBM-bound;
   learned  the learned T^{mu nu} correction, scaled down (128 paired training
            runs x 5 snapshots = 1.3e6 samples, and 64 evaluation instances, at
            N_z = 2048 instead of 8192):
            R-SLB(4;8) + features + network against the plain R-SLB(4;128)
            solve, wall time and relative T^{mu nu} error at t = 0.25.
+The first three carry a "cpu_baseline" of the oracle on a bounded sample.
 """
 import argparse
 import hashlib
@@ -64,9 +69,9 @@ def parse():
     ap.add_argument("--variants", default=None,
                     help="comma-separated stage-kernel variant per velocity class (-1: empty), and an eighth "
                          "for the whole batch as one class (-1: per class); skips the autotuner")
-    ap.add_argument("--aux", default="all", choices=("none", "all", "bjorken", "ensemble", "learned"),
-                    help="also measure the Bjorken batch, the uneven Sod ensemble and the learned correction "
-                         "(all), or one of them")
+    ap.add_argument("--aux", default="all", choices=("none", "all", "c1", "bjorken", "ensemble", "learned"),
+                    help="also measure the near-inviscid tube, the Bjorken batch, the uneven Sod ensemble and "
+                         "the learned correction (all), or one of them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy five times (the reference kernel for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -160,7 +165,62 @@ def _events(torch, stream, fn, reps=1):
     return e0.elapsed_time(e1) * 1e-3
 
 
-def bjorken_leg(torch, rsl, stream, n=4096, window=1000, seed=3):
+def _oracle_rate(fn, updates, sample):
+    """Single-threaded oracle on a bounded sample: updates/s and what was run."""
+    t0 = time.perf_counter()
+    fn()
+    return dict(value=updates / (time.perf_counter() - t0), unit="updates/s", cores=1, kind="oracle",
+                sample=sample)
+
+
+def c1_leg(torch, rsl, stream, cpu=True):
+    """The near-inviscid tube: N_z = 400, R-SLB(3;8), tau_r = 1e-3, dt = 1.25e-3,
+    200 steps (launch-bound, not HBM-bound): updates/s of the whole run as a
+    one-instance batch replayed from graphs of 10 steps, and as eager
+    single-instance steps.  Parity: one more batch step from the final state
+    against one oracle step from that same state; and the final state against
+    the oracle's 200-step run (the CPU baseline's sample), beside the spread
+    of the oracle itself under a one-ulp perturbation of its input (WENO5
+    without a regulariser amplifies rounding differences near the fronts)."""
+    import numpy as np
+    import oracle
+    nz, dt, steps = 400, 1.25e-3, 200
+    quad = rsl.Quadrature(QL, 8, 3)
+    prob = rsl.make_problem(nz=nz, tau_r=1e-3, nL=1.0, TL=1.0, nR=0.4, TR=0.8)
+    B = rsl.Batch([quad], [prob], [dt])
+    B.init(stream=stream)
+    B.graph_step(10, stream=stream)
+    B.init(stream=stream)
+    sec = _events(torch, stream, lambda: B.graph_step(10, stream=stream), reps=steps // 10)
+    got = B.f(0).cpu().numpy()
+    B.step(1, stream=stream)
+    one = B.f(0).cpu().numpy()
+    inst = rsl.Instance(quad, prob)
+    inst.init(stream=stream)
+    inst.step(dt, 10, stream=stream)
+    sec_eager = _events(torch, stream, lambda: inst.step(dt, steps, stream=stream))
+    S = oracle.Sod(oracle.VelocitySet(QL, 8, 3), nz, nL=1.0, TL=1.0, nR=0.4, TR=0.8, tau_r=1e-3,
+                   bc=oracle.BC_OUTFLOW)
+    f0 = S.init()
+    t0 = time.perf_counter()
+    ref = S.run(f0, dt, steps)
+    cpu_s = time.perf_counter() - t0
+    rel = lambda x, y: float(np.max(np.abs(x - y)) / np.max(np.abs(y)))
+    pert = S.run(f0 * (1 + 1.1e-16 * np.random.default_rng(0).standard_normal(f0.shape)), dt, steps)
+    updates = 3.0 * nz * quad.V * steps
+    out = {"workload": "Sod near-inviscid: N_z = 400, Q_L = 3, Q_xi = 8, N_Omega = 3, tau_r = 1e-3, "
+                       "dt = 1.25e-3, 200 steps, f64",
+           "value": updates / sec, "unit": "updates/s", "seconds": sec,
+           "eager_single_instance_updates_per_s": updates / sec_eager,
+           "one_step_rel_err_vs_oracle": rel(one, S.run(got, dt, 1)),
+           "run_rel_err_vs_oracle": rel(got, ref), "oracle_one_ulp_envelope": rel(pert, ref)}
+    if cpu:
+        out["cpu_baseline"] = dict(value=updates / cpu_s, unit="updates/s", cores=1, kind="oracle",
+                                   sample="the whole 200-step run (single-threaded plain C)")
+    return out
+
+
+def bjorken_leg(torch, rsl, stream, n=4096, window=1000, seed=3, cpu=True):
     import numpy as np
     rng = np.random.default_rng(seed)
     quads, qs, probs = {}, [], []
@@ -183,14 +243,24 @@ def bjorken_leg(torch, rsl, stream, n=4096, window=1000, seed=3):
     assert rc == 0, "non-finite Bjorken instance %d" % bad
     updates = 3.0 * window * sum(q.V for q in qs)
     tflops = 3.0 * window * flop_stage / sec / 1e12
-    return {"workload": "4096 Bjorken runs, Q_xi uniform in {20..200}, Q_L = 3, 1000 steps of dtau = 1e-3, f64",
-            "value": updates / sec, "unit": "updates/s", "seconds": sec,
-            "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": round(tflops / FP64_MFMA_PEAK_TFLOPS, 4),
-                         "kernel": "bj_mfma_kernel (K^P F, 2 Q_xi^2 Q_L flop per instance and stage)"}}
+    out = {"workload": "4096 Bjorken runs, Q_xi uniform in {20..200}, Q_L = 3, 1000 steps of dtau = 1e-3, f64",
+           "value": updates / sec, "unit": "updates/s", "seconds": sec,
+           "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(tflops / FP64_MFMA_PEAK_TFLOPS, 4),
+                        "kernel": "bj_mfma_kernel (K^P F, 2 Q_xi^2 Q_L flop per instance and stage)"}}
+    if cpu:
+        import oracle
+        sample = [(int(q.Q), p.tau_aw0) for q, p in zip(qs[:8], probs[:8])]
+        runs = [oracle.Bjorken(oracle.VelocitySet(QL, Q, 4), tau_mode=oracle.TAU_ETAS, tau_aw0=taw)
+                for Q, taw in sample]
+        out["cpu_baseline"] = _oracle_rate(lambda: [R.run(R.init(), 1.0, 1e-3, window) for R in runs],
+                                           3.0 * window * sum(QL * Q for Q, _ in sample),
+                                           "the first 8 runs of the batch, the same %d-step window each "
+                                           "(single-threaded plain C)" % window)
+    return out
 
 
-def ensemble_leg(torch, rsl, stream, n=1024, steps=20, chunk=10, seed=4):
+def ensemble_leg(torch, rsl, stream, n=1024, steps=100, chunk=10, seed=4, cpu=True):
     import numpy as np
     rng = np.random.default_rng(seed)
     quads = {Q: rsl.Quadrature(QL, Q, min(Q - 1, 4)) for Q in (8, 16, 32, 64)}
@@ -214,13 +284,23 @@ def ensemble_leg(torch, rsl, stream, n=1024, steps=20, chunk=10, seed=4):
     cellvel = sum(p.nz * q.V for p, q in zip(probs, qs))
     updates = 3.0 * cellvel * steps
     gbs = 32.0 * cellvel * steps / sec / 1e9
-    return {"workload": "1024 uneven Sod instances, N_z log-uniform in [256, 16384], Q_xi in {8,16,32,64}, f32",
+    out = {"workload": "1024 uneven Sod instances, N_z log-uniform in [256, 16384], Q_xi in {8,16,32,64}, f32, "
+                       "graph replays of 10 steps, 100 steps",
             "value": updates / sec, "unit": "updates/s", "ms_per_step": sec / steps * 1e3,
             "f_bytes_per_field": 4 * cellvel,
             "variants": [B.variant(c)[0] for c in range(rsl.N_CLASSES + 1)],
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4),
                          "kernel": "Sod stage kernels of all classes, 32 B per cell-velocity and step"}}
+    if cpu:
+        import oracle
+        p0, q0 = probs[0], qs[0]
+        S = oracle.Sod(oracle.VelocitySet(QL, q0.Q, min(q0.Q - 1, 4)), p0.nz, nL=1.0, TL=1.0, nR=p0.n_R, TR=p0.T_R,
+                       tau_r=p0.tau_r, bc=oracle.BC_OUTFLOW, store_f32=True)
+        out["cpu_baseline"] = _oracle_rate(lambda: S.run(S.init(), dts[0], 5), 3.0 * 5 * p0.nz * q0.V,
+                                           "5 steps of the batch's first instance (N_z = %d, V = %d), "
+                                           "single-threaded plain C" % (p0.nz, q0.V))
+    return out
 
 
 def learned_leg(torch, stream):
@@ -337,8 +417,10 @@ def main():
         "roofline": roof,
     }
     if a.aux != "none":
-        legs = {"bjorken": lambda: bjorken_leg(torch, rsl, stream),
-                "ensemble": lambda: ensemble_leg(torch, rsl, stream),
+        cpu = not a.no_cpu_baseline
+        legs = {"c1": lambda: c1_leg(torch, rsl, stream, cpu),
+                "bjorken": lambda: bjorken_leg(torch, rsl, stream, cpu=cpu),
+                "ensemble": lambda: ensemble_leg(torch, rsl, stream, cpu=cpu),
                 "learned": lambda: learned_leg(torch, stream)}
         with torch.cuda.stream(stream):
             out["aux"] = {k: fn() for k, fn in legs.items() if a.aux in ("all", k)}
