@@ -176,8 +176,8 @@ def _oracle_rate(fn, updates, sample):
 def c1_leg(torch, rsl, stream, cpu=True):
     """The near-inviscid tube: N_z = 400, R-SLB(3;8), tau_r = 1e-3, dt = 1.25e-3,
     200 steps (launch-bound, not HBM-bound): updates/s of the whole run as a
-    one-instance batch replayed from graphs of 10 steps, and as eager
-    single-instance steps.  Parity: one more batch step from the final state
+    one-instance batch (autotuned on a developed state) replayed from graphs
+    of 10 steps, and as eager single-instance steps.  Parity: one more batch step from the final state
     against one oracle step from that same state; and the final state against
     the oracle's 200-step run (the CPU baseline's sample), beside the spread
     of the oracle itself under a one-ulp perturbation of its input (WENO5
@@ -188,6 +188,9 @@ def c1_leg(torch, rsl, stream, cpu=True):
     quad = rsl.Quadrature(QL, 8, 3)
     prob = rsl.make_problem(nz=nz, tau_r=1e-3, nL=1.0, TL=1.0, nR=0.4, TR=0.8)
     B = rsl.Batch([quad], [prob], [dt])
+    B.init(stream=stream)
+    B.step(20, stream=stream)
+    B.autotune(reps=3, stream=stream)
     B.init(stream=stream)
     B.graph_step(10, stream=stream)
     B.init(stream=stream)
@@ -212,6 +215,7 @@ def c1_leg(torch, rsl, stream, cpu=True):
                        "dt = 1.25e-3, 200 steps, f64",
            "value": updates / sec, "unit": "updates/s", "seconds": sec,
            "eager_single_instance_updates_per_s": updates / sec_eager,
+           "variants": [B.variant(c)[0] for c in range(rsl.N_CLASSES + 1)],
            "one_step_rel_err_vs_oracle": rel(one, S.run(got, dt, 1)),
            "run_rel_err_vs_oracle": rel(got, ref), "oracle_one_ulp_envelope": rel(pert, ref)}
     if cpu:
