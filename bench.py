@@ -23,9 +23,9 @@ object carries four further measurements on seeded synthetic inputs:
            log-uniform in [1e-4, 1], dt = min(0.5/N_z, tau_r/2)), f in
            binary32, 100 steps in graph replays of 10; 1.4 GB per field,
            so HBM-bound;
-  learned  the learned T^{mu nu} correction, scaled down (128 paired training
-           runs x 5 snapshots = 1.3e6 samples, and 64 evaluation instances, at
-           N_z = 2048 instead of 8192):
+  learned  the learned T^{mu nu} correction, scaled down (2048 paired
+           training runs x 5 snapshots x 2048 cells = 2.1e7 samples, 100
+           epochs, and 64 evaluation instances, at N_z = 2048 instead of 8192):
            R-SLB(4;8) + features + network against the plain R-SLB(4;128)
            solve, wall time and relative T^{mu nu} error at t = 0.25.
 The first three carry a "cpu_baseline" of the oracle on a bounded sample.
@@ -163,6 +163,11 @@ def _events(torch, stream, fn, reps=1):
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) * 1e-3
+
+
+def _progress(msg):
+    """One line per finished part of the run, on stderr (the JSON line is stdout's only line)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def _oracle_rate(fn, updates, sample):
@@ -310,7 +315,8 @@ def ensemble_leg(torch, rsl, stream, n=1024, steps=100, chunk=10, seed=4, cpu=Tr
 def learned_leg(torch, stream):
     from paper_1612_01287_amd import learned
     t0 = time.perf_counter()
-    X, T = learned.generate(n_runs=1024, nz=2048, t_snaps=(0.05, 0.1, 0.15, 0.2, 0.25), seed=5, q_lo=8, q_hi=128)
+    X, T = learned.generate(n_runs=2048, nz=2048, t_snaps=(0.05, 0.1, 0.15, 0.2, 0.25), seed=5, q_lo=8, q_hi=128)
+    _progress("learned: %d training samples generated (%.1f s)" % (X.shape[0], time.perf_counter() - t0))
     corr, hist = learned.train(X, T, epochs=100, batch=8192, lr=2e-3, seed=1, margin=0.25)
     torch.cuda.synchronize()
     prep = time.perf_counter() - t0
@@ -401,6 +407,7 @@ def main():
     value = updates_per_step * a.steps / el
     with torch.cuda.stream(stream):
         roof = kernel_roofline(torch, B, a.dtype, updates_per_step, variants, chunk, stream)
+    _progress("sweep: %d steps in %.3f s" % (a.steps, el))
     out = {
         "metric": "distribution updates/s (cells x velocities x RK stages)",
         "value": value,
@@ -426,10 +433,16 @@ def main():
                 "bjorken": lambda: bjorken_leg(torch, rsl, stream, cpu=cpu),
                 "ensemble": lambda: ensemble_leg(torch, rsl, stream, cpu=cpu),
                 "learned": lambda: learned_leg(torch, stream)}
+        out["aux"] = {}
         with torch.cuda.stream(stream):
-            out["aux"] = {k: fn() for k, fn in legs.items() if a.aux in ("all", k)}
+            for k, fn in legs.items():
+                if a.aux in ("all", k):
+                    t0 = time.perf_counter()
+                    out["aux"][k] = fn()
+                    _progress("aux leg %s done (%.1f s)" % (k, time.perf_counter() - t0))
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.dtype)
+        _progress("oracle baseline done")
     print(json.dumps(out))
 
 
