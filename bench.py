@@ -152,7 +152,10 @@ def kernel_roofline(torch, B, dtype, updates_per_step, variants, chunk, stream, 
                 kernel="Sod stage launch group (one RK stage of all velocity classes; mean over %d graph-replayed "
                        "stages)" % (3 * chunk * reps), avg_launch_us=round(ms * 1e3, 2),
                 bytes_per_launch=bytes_per_launch, variants=variants, kernel_forms=kernel_forms(variants),
-                kernel_source_hash=kernel_source_hash())
+                kernel_source_hash=kernel_source_hash(),
+                residency="the sweep's three fields (%.0f MB) fit in the 256 MB last-level cache, so part of the "
+                          "traffic is served there; the HBM-resident case is the ensemble aux leg"
+                          % (3 * BYTES_PER_CELL_VEL_STEP[dtype] / 8 * cell_vel / 1e6))
 
 
 def _events(torch, stream, fn, reps=1):
