@@ -10,7 +10,7 @@ Metric: distribution updates per second, one update = one (cell, velocity,
 RK stage).
 
 Prints one JSON line (see the repository's measurement contract).  Its "aux"
-object carries four further measurements on seeded synthetic inputs:
+object carries five further measurements on seeded synthetic inputs:
   c1       the near-inviscid tube (N_z = 400, R-SLB(3;8), tau_r = 1e-3,
            dt = 1.25e-3, 200 steps), launch-bound: updates/s and the last
            step against the oracle;
@@ -23,6 +23,8 @@ object carries four further measurements on seeded synthetic inputs:
            log-uniform in [1e-4, 1], dt = min(0.5/N_z, tau_r/2)), f in
            binary32, 100 steps in graph replays of 10; 1.4 GB per field,
            so HBM-bound;
+  scaled   the sweep's 16 instances x 256 copies (16.5 GB per field, FP64),
+           out of the last-level cache: 20 steps timed after 1000;
   learned  the learned T^{mu nu} correction, scaled down (2048 paired
            training runs x 5 snapshots x 2048 cells = 2.1e7 samples, 100
            epochs, and 64 evaluation instances, at N_z = 2048 instead of 8192):
@@ -69,9 +71,10 @@ def parse():
     ap.add_argument("--variants", default=None,
                     help="comma-separated stage-kernel variant per velocity class (-1: empty), and an eighth "
                          "for the whole batch as one class (-1: per class); skips the autotuner")
-    ap.add_argument("--aux", default="all", choices=("none", "all", "c1", "bjorken", "ensemble", "learned"),
-                    help="also measure the near-inviscid tube, the Bjorken batch, the uneven Sod ensemble and "
-                         "the learned correction (all), or one of them")
+    ap.add_argument("--aux", default="all", choices=("none", "all", "c1", "bjorken", "ensemble", "scaled",
+                                                           "learned"),
+                    help="also measure the near-inviscid tube, the Bjorken batch, the uneven Sod ensemble, the "
+                         "sweep scaled out of the cache and the learned correction (all), or one of them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy five times (the reference kernel for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -230,6 +233,41 @@ def c1_leg(torch, rsl, stream, cpu=True):
         out["cpu_baseline"] = dict(value=updates / cpu_s, unit="updates/s", cores=1, kind="oracle",
                                    sample="the whole 200-step run (single-threaded plain C)")
     return out
+
+
+def scaled_leg(torch, rsl, stream, copies=256, dev_steps=1000, steps=20, chunk=10):
+    """The sweep scaled out of the last-level cache: 256 copies of each of its
+    16 instances (4096 instances, 49.5 GB in the three f fields, FP64), run
+    for 1000 steps (the state the headline's variants are tuned on), tuned,
+    then 20 steps timed in graph replays of 10."""
+    quads, probs, dts = [], [], []
+    for Q in QXI:
+        quad = rsl.Quadrature(QL, Q, NOM)
+        for es in ETAS:
+            for _ in range(copies):
+                quads.append(quad)
+                probs.append(rsl.make_problem(nz=NZ, bc="outflow", tau_mode="etas", tau_aw0=0.3854 * es,
+                                              nL=1.0, TL=1.0, nR=0.4, TR=0.8))
+                dts.append(0.5 / NZ)
+    B = rsl.Batch(quads, probs, dts)
+    B.init(stream=stream)
+    B.step(dev_steps, stream=stream)
+    B.autotune(reps=3, stream=stream)
+    B.graph_step(chunk, stream=stream)
+    sec = _events(torch, stream, lambda: B.graph_step(chunk, stream=stream), reps=steps // chunk)
+    rc, bad = B.status(stream)
+    assert rc == 0, "non-finite scaled-sweep instance %d" % bad
+    cellvel = sum(p.nz * q.V for p, q in zip(probs, quads))
+    updates = 3.0 * cellvel * steps
+    gbs = BYTES_PER_CELL_VEL_STEP["f64"] * cellvel * steps / sec / 1e9
+    return {"workload": "the sweep x 256 copies: 4096 Sod instances, N_z = 4096, Q_xi in {8,16,40,100}, "
+                        "eta/s in {0.01,0.1,1,10}, f64, steps 1000-1020",
+            "value": updates / sec, "unit": "updates/s", "ms_per_step": sec / steps * 1e3,
+            "f_bytes_per_field": 8 * cellvel,
+            "variants": [B.variant(c)[0] for c in range(rsl.N_CLASSES + 1)],
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "kernel": "Sod stage kernels of the whole batch, 64 B per cell-velocity and step"}}
 
 
 def bjorken_leg(torch, rsl, stream, n=4096, window=1000, seed=3, cpu=True):
@@ -435,6 +473,7 @@ def main():
         legs = {"c1": lambda: c1_leg(torch, rsl, stream, cpu),
                 "bjorken": lambda: bjorken_leg(torch, rsl, stream, cpu=cpu),
                 "ensemble": lambda: ensemble_leg(torch, rsl, stream, cpu=cpu),
+                "scaled": lambda: scaled_leg(torch, rsl, stream),
                 "learned": lambda: learned_leg(torch, stream)}
         out["aux"] = {}
         with torch.cuda.stream(stream):
