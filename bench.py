@@ -21,7 +21,7 @@ object carries five further measurements on seeded synthetic inputs:
   ensemble 1024 uneven Sod instances (N_z log-uniform in [256, 16384],
            Q_xi in {8, 16, 32, 64}, T_L/T_R uniform in [1.1, 3], tau_r
            log-uniform in [1e-4, 1], dt = min(0.5/N_z, tau_r/2)), f in
-           binary32, 100 steps in graph replays of 10; 1.4 GB per field,
+           binary32, 200 steps in graph replays of 100; 1.4 GB per field,
            so HBM-bound;
   scaled   the sweep's 16 instances x 128 copies (8.3 GB per field, FP64),
            out of the last-level cache: 20 steps timed after 1000;
@@ -311,7 +311,7 @@ def bjorken_leg(torch, rsl, stream, n=4096, window=1000, seed=3, cpu=True):
     return out
 
 
-def ensemble_leg(torch, rsl, stream, n=1024, steps=100, chunk=10, seed=4, cpu=True):
+def ensemble_leg(torch, rsl, stream, n=1024, steps=200, chunk=100, seed=4, cpu=True):
     import numpy as np
     rng = np.random.default_rng(seed)
     quads = {Q: rsl.Quadrature(QL, Q, min(Q - 1, 4)) for Q in (8, 16, 32, 64)}
@@ -336,7 +336,7 @@ def ensemble_leg(torch, rsl, stream, n=1024, steps=100, chunk=10, seed=4, cpu=Tr
     updates = 3.0 * cellvel * steps
     gbs = 32.0 * cellvel * steps / sec / 1e9
     out = {"workload": "1024 uneven Sod instances, N_z log-uniform in [256, 16384], Q_xi in {8,16,32,64}, f32, "
-                       "graph replays of 10 steps, 100 steps",
+                       "graph replays of 100 steps, 200 steps",
             "value": updates / sec, "unit": "updates/s", "ms_per_step": sec / steps * 1e3,
             "f_bytes_per_field": 4 * cellvel,
             "variants": [B.variant(c)[0] for c in range(rsl.N_CLASSES + 1)],
