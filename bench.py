@@ -57,7 +57,7 @@ STEPS = 2000        # RK3 steps of the sweep (t = 0.244 at dt = 0.5 / N_z)
 # counters (scaled by a plain copy kernel's readings); valid only for the
 # kernel sources and variants they were taken with
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sod_stage_c2_traffic.txt")
-KERNEL_SOURCES = ("sod_stage.h", "sod_stage_f64.hip", "sod_stage_f32.hip", "rsl_math.h", "rsl_impl.h")
+KERNEL_SOURCES = ("sod_stage.h", "sod_split.h", "sod_stage_f64.hip", "sod_stage_f32.hip", "rsl_math.h", "rsl_impl.h")
 
 
 def parse():

@@ -318,7 +318,6 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
     constexpr int G = kGroup;
     constexpr int WN = kWin;
     constexpr int step = W * NV;
-    const int V = d.V;
     const int lane = threadIdx.x & (kLanes - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     const int z0 = tile * kTileCells;
@@ -362,31 +361,50 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
 
     unsigned bad = 0;
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
-    // Rounds of W NV velocities: the loads of rounds r + 1 .. r + K - 1 are
-    // issued before round r is computed, into other register sets (no copies
-    // between them, so nothing waits for the loads in flight).  Loads are
-    // unconditional (indices clamped into the field) so that the compiler's
-    // wait counts stay exact; the halo lanes' second load is, on other lanes,
-    // a repeat of their own cell.
+    // Rounds of W NV velocities, angular-node blocks outer and radial nodes
+    // inner: round (J-block jb, radial node k) gives wave w the velocities
+    // v = k Q_xi + J, J = jb + w + i W, so that a wave meets each angular node
+    // J in Q_L consecutive rounds and forms the Legendre sums of f^eq over m
+    // (which depend on J only) once for all of them.  The loads of rounds
+    // r + 1 .. r + K - 1 are issued before round r is computed, into other
+    // register sets (no copies between them, so nothing waits for the loads
+    // in flight).  Loads are unconditional (indices clamped into the field) so
+    // that the compiler's wait counts stay exact; the halo lanes' second load
+    // is, on other lanes, a repeat of their own cell.
+    const int Q = d.Q, QL = d.QL;
+    const int nrounds = (Q + step - 1) / step * QL;
+    struct Pos {
+        int jb, k;
+    };
+    auto advance = [&](Pos& p) {
+        if (++p.k == QL) {
+            p.k = 0;
+            p.jb += step;
+        }
+    };
     const int hcl = lane < 5 ? hcc : cc;
-    auto load_round = [&](int vb, Tf (&a)[NV], Tf (&h)[NV], Tf (&n)[NV]) {
+    auto load_round = [&](const Pos& p, Tf (&a)[NV], Tf (&h)[NV], Tf (&n)[NV]) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const int v = min(vb + w + i * W, V - 1);
+            const int v = p.k * Q + min(p.jb + w + i * W, Q - 1);
             const Tf* row = fcur + (size_t)v * pitch;
             a[i] = row[cc];
             h[i] = row[hcl];
             if (STAGE > 1) n[i] = fn[(size_t)v * pitch + cc];
         }
     };
-    auto round = [&](int vbase, const Tf (&ra)[NV], const Tf (&rh)[NV], const Tf (&rn)[NV]) {
+    double gJ[NV], hJ[NV];   // Legendre sums of the coefficients at the wave's angular nodes
+#pragma unroll
+    for (int i = 0; i < NV; ++i) gJ[i] = hJ[i] = 0.0;
+    auto round = [&](const Pos& p, const Tf (&ra)[NV], const Tf (&rh)[NV], const Tf (&rn)[NV]) {
 #pragma unroll
         for (int i0 = 0; i0 < NV; i0 += G) {
-            if (vbase + w + i0 * W >= V) break;
+            if (p.jb + w + i0 * W >= Q) break;
 #pragma unroll
             for (int i = i0; i < i0 + G && i < NV; ++i) {
-                const int v = vbase + w + i * W;
-                if (v < V) {
+                const int J = p.jb + w + i * W;
+                if (J < Q) {
+                    const int v = p.k * Q + J;
                     double fc = (double)ra[i], h = (double)rh[i];
                     if (eqbc) {
                         const double gl = ldc(d.feqL, v), gr = ldc(d.feqR, v);
@@ -402,8 +420,9 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
             wave_lds_sync();
 #pragma unroll
             for (int i = i0; i < i0 + G && i < NV; ++i) {
-                const int v = vbase + w + i * W;
-                if (v < V) {
+                const int J = p.jb + w + i * W;
+                if (J < Q) {
+                    const int v = p.k * Q + J;
                     const __attribute__((address_space(4))) double* vr =
                         (const __attribute__((address_space(4))) double*)d.tab.vrec + (size_t)v * kVrec;
                     const double x = vr[0];
@@ -418,13 +437,18 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
                     double y = (double)(Tf)(sv[2] + dt * (-(F - Fm) * dzi));
                     if (collide) {
                         const double l1 = vr[2], wx = vr[3];
-                        double gsum = 0.0;
+                        if (p.k == 0) {   // first radial node of this J: its sums over m
+                            double g = 0.0, hs = 0.0;
 #pragma unroll
-                        for (int m = 0; m <= kMaxNOm; ++m)
-                            if (m <= d.NOm)
-                                gsum = fma(vr[4 + m], fma(l1, cfl[(3 + kMaxNOm + m) * kLanes], cfl[(2 + m) * kLanes]),
-                                           gsum);
-                        y += dt * (cA - cB * x) * (wx * gsum - sv[2]);
+                            for (int m = 0; m <= kMaxNOm; ++m)
+                                if (m <= d.NOm) {
+                                    g = fma(vr[4 + m], cfl[(2 + m) * kLanes], g);
+                                    hs = fma(vr[4 + m], cfl[(3 + kMaxNOm + m) * kLanes], hs);
+                                }
+                            gJ[i] = g;
+                            hJ[i] = hs;
+                        }
+                        y += dt * (cA - cB * x) * (wx * fma(l1, hJ[i], gJ[i]) - sv[2]);
                     }
                     double out;
                     if (STAGE == 1) out = y;
@@ -435,12 +459,12 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
                         if (!isfinite((double)o)) bad |= 2u;
                         fout[(size_t)v * pitch + c] = o;
                         // moments of the stored output (the next stage's field)
-                        const double fo = (double)o, p = vr[1] * fo;
+                        const double fo = (double)o, pw = vr[1] * fo;
                         m0 += fo;
                         m1 += x * fo;
-                        m2 += p;
-                        m3 += x * p;
-                        m4 += x * x * p;
+                        m2 += pw;
+                        m3 += x * pw;
+                        m4 += x * x * pw;
                     }
                 }
             }
@@ -450,15 +474,20 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
     // a ring of K register sets: round r is computed while rounds r + 1 ..
     // r + K - 1 are in flight
     Tf A[K][NV], H[K][NV], N[K][NV];
+    Pos lp{0, 0}, cp{0, 0};
 #pragma unroll
-    for (int k = 0; k < K - 1; ++k) load_round(k * step, A[k], H[k], N[k]);
-    for (int vbase = 0; vbase < V; vbase += K * step) {
+    for (int k = 0; k < K - 1; ++k) {
+        load_round(lp, A[k], H[k], N[k]);
+        advance(lp);
+    }
+    for (int r0 = 0; r0 < nrounds; r0 += K) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int vb = vbase + k * step;
-            if (vb >= V) break;
-            load_round(vb + (K - 1) * step, A[(k + K - 1) % K], H[(k + K - 1) % K], N[(k + K - 1) % K]);
-            round(vb, A[k], H[k], N[k]);
+            if (r0 + k >= nrounds) break;
+            load_round(lp, A[(k + K - 1) % K], H[(k + K - 1) % K], N[(k + K - 1) % K]);
+            advance(lp);
+            round(cp, A[k], H[k], N[k]);
+            advance(cp);
         }
     }
     if (bad) atomicOr(d.status, bad);
