@@ -14,8 +14,11 @@ Parity status per function (pins in tests/test_oracle_*.py):
   a~_{l,m}, f^eq .............. pinned (App. A closed forms and series, MJ moments)
   Landau frame ................ pinned (round trip, 2x2 eigenproblem)
   WENO5 ....................... pinned (constants, limiting cases, 5th order)
+  relaxation-time laws ........ pinned (printed tau_{A-W;0}, tau_L/tau_R of eqs. tau_LR,
+                                tau_LR2; Bjorken ideal gas against eq. bjorken_tauAW_mu)
   Sod step .................... pinned (conservation, uniform state, reflection,
-                                ballistic staircase, inviscid Riemann plateau)
+                                ballistic staircase, inviscid Riemann plateau,
+                                3rd order in dt, 5th order in dz for free streaming)
   Bjorken step ................ pinned (tau n = 1, energy identity, free streaming,
                                 ideal-fluid limit, 3rd-order RK convergence)
 """
@@ -67,6 +70,8 @@ def lib():
         L.o_sod_L.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.o_sod_run.restype = ctypes.c_int
         L.o_sod_run.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.c_int]
+        L.o_relax_time.restype = ctypes.c_double
+        L.o_relax_time.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
         L.o_sod_init.restype = None
         L.o_sod_init.argtypes = [ctypes.c_void_p, _dp]
         L.o_bj_L.restype = ctypes.c_int
@@ -184,6 +189,10 @@ class Sod:
         f = np.zeros((self.vs.V, self.nz))
         lib().o_sod_init(ctypes.byref(self.s), _p(f))
         return f
+
+    def relax_time(self, n, T):
+        """tau_AW of a cell with Landau-frame density n and temperature T."""
+        return lib().o_relax_time(ctypes.byref(self.s), float(n), float(T))
 
     def L(self, f):
         f = _c(f)

@@ -239,7 +239,8 @@ typedef struct {
     const double *feqL, *feqR;   /* [V] ghost states for bc = 0 */
 } o_sod_t;
 
-static double o_relax_time(const o_sod_t *S, double n, double T)
+/* Relaxation time of one Sod cell (exported so that tests can pin it). */
+double o_relax_time(const o_sod_t *S, double n, double T)
 {
     if (S->tau_mode == 0) return S->tau_r;
     /* eq. Sod:tau with lambda_bar = n / T^3 (eq. lambda) */
