@@ -1,38 +1,42 @@
 """Throughput of the R-SLB Sod step on one MI355X.
 
-Workload (the finite-viscosity shock-tube sweep): N_z = 4096 cells on
-z in [-0.5, 0.5], (T, n)_L = (1, 1), (T, n)_R = (0.8, 0.4), outflow ghosts,
-Q_L = 3 radial nodes, Q_xi in {8, 16, 40, 100}, N_Omega = 4, eta/s in
-{0.01, 0.1, 1, 10} with tau_AW0 = 0.3854 eta/s (relaxation-time law of
-eq. Sod:tau), dt = 0.5 / N_z, f in binary64 -- sixteen instances.  One step =
-one TVD-RK3 step (three fused stage kernels) of all sixteen instances.
-Metric: distribution updates per second, one update = one (cell, velocity,
-RK stage).
+Headline workload (the uneven shock-tube ensemble, HBM-resident): 1024 Sod
+instances drawn with numpy's default_rng(4): N_z log-uniform in [256, 16384]
+(rounded), Q_xi uniform in {8, 16, 32, 64} with Q_L = 3 and
+N_Omega = min(Q_xi - 1, 4), (T, n)_L = (1, 1), T_R = T_L / r with r uniform in
+[1.1, 3] and n_R = T_R^3, tau_r log-uniform in [1e-4, 1] (constant),
+dt_i = min(0.5 / N_z, tau_r / 2), zero-gradient ghosts; f stored in binary32,
+per-cell work (moments, Landau frame, tau, f^eq coefficients) in binary64.
+The whole batch runs as one class in the loop form, in captured graphs of
+`chunk` RK3 steps.  Before timing, the ensemble is advanced by --dev-steps
+steps (so the flows have developed) and the stage-kernel shapes are tuned on
+that state; timing continues from there.  One step = one TVD-RK3 step of
+every instance.  Metric: distribution updates per second, one update = one
+(cell, velocity, RK stage); the roofline is the HBM one, with 32 B per
+cell-velocity and step (f_n read by the three stages, stage fields read
+twice, three stores) over the mean duration of one RK stage of the whole
+batch, from HIP events on the launching stream around the timed replays.
 
-Prints one JSON line (see the repository's measurement contract).  Its "aux"
-object carries five further measurements on seeded synthetic inputs:
+Prints one JSON line.  Its "aux" object carries further measurements:
+  sweep    the finite-viscosity tube sweep (16 instances, N_z = 4096,
+           Q_xi in {8, 16, 40, 100}, eta/s in {0.01, 0.1, 1, 10}), binary64;
+           its three fields (193 MB) fit in the 256 MB last-level cache;
   c1       the near-inviscid tube (N_z = 400, R-SLB(3;8), tau_r = 1e-3,
-           dt = 1.25e-3, 200 steps), launch-bound: updates/s and the last
-           step against the oracle;
+           dt = 1.25e-3, 200 steps), launch-bound;
   bjorken  4096 Bjorken runs (T0 log-uniform in [0.5, 2] GeV, eta/s
            log-uniform in [0.01, 10], Q_xi uniform in {20..200}, Q_L = 3,
-           ideal gas), a 1000-step window at dtau = 1e-3 in one launch; the
-           K^P F product on the matrix cores against the FP64 MFMA peak;
-  ensemble 1024 uneven Sod instances (N_z log-uniform in [256, 16384],
-           Q_xi in {8, 16, 32, 64}, T_L/T_R uniform in [1.1, 3], tau_r
-           log-uniform in [1e-4, 1], dt = min(0.5/N_z, tau_r/2)), f in
-           binary32, 200 steps in graph replays of 100; 1.4 GB per field,
-           so HBM-bound;
-  scaled   the sweep's 16 instances x 128 copies (8.3 GB per field, FP64),
-           out of the last-level cache: 20 steps timed after 1000;
-  learned  the learned T^{mu nu} correction, scaled down (2048 paired
-           training runs x 5 snapshots x 2048 cells = 2.1e7 samples, 100
-           epochs, and 64 evaluation instances, at N_z = 2048 instead of 8192):
-           R-SLB(4;8) + features + network against the plain R-SLB(4;128)
-           solve, wall time and relative T^{mu nu} error at t = 0.25.
-The first three carry a "cpu_baseline" of the oracle on a bounded sample.
+           ideal gas), a 1000-step window on the matrix cores;
+  scaled   the sweep's 16 instances x 128 copies (24.8 GB in the three
+           binary64 fields), out of the last-level cache;
+  learned  the learned T^{mu nu} correction (training on 2.1e7 samples from
+           2048 paired runs at N_z = 2048, evaluation on 64 instances);
+  learned_c5 (only on request) the learned correction evaluated at full
+           size: 512 instances x N_z = 8192 against R-SLB(4;128).
+The oracle (plain C) is timed on the host's cores on a bounded sample of the
+headline workload ("cpu_baseline"), and single-threaded beside each aux leg.
 """
 import argparse
+import concurrent.futures
 import hashlib
 import json
 import os
@@ -42,58 +46,94 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-QXI = (8, 16, 40, 100)
-ETAS = (0.01, 0.1, 1.0, 10.0)
-NZ = 4096
 QL = 3
-NOM = 4
-BYTES_PER_CELL_VEL_STEP = {"f64": 64, "f32": 32}   # f_n read 3x, stage fields read 2x, written 3x
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
-HBARC = 0.1973269804      # GeV fm
-CHUNK = 10          # RK3 steps per captured HIP graph
-STEPS = 2000        # RK3 steps of the sweep (t = 0.244 at dt = 0.5 / N_z)
-# HBM bytes per stage launch group read from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# counters (scaled by a plain copy kernel's readings); valid only for the
-# kernel sources and variants they were taken with
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sod_stage_c2_traffic.txt")
+HBARC = 0.1973269804                       # GeV fm
+TAU_AW0_PER_ETAS = 5 * HBARC / (0.4 * 6.4)  # eq. Sod:tau at T_ref = 0.4 GeV, L_ref = 6.4 fm
+BYTES_PER_CELL_VEL_STEP = {"f64": 64, "f32": 32}   # f_n read 3x, stage fields read 2x, written 3x
+# sweep workload
+SWEEP_QXI = (8, 16, 40, 100)
+SWEEP_ETAS = (0.01, 0.1, 1.0, 10.0)
+SWEEP_NZ = 4096
+# uneven ensemble workload
+ENS_N, ENS_SEED = 1024, 4
 KERNEL_SOURCES = ("sod_stage.h", "sod_split.h", "sod_stage_f64.hip", "sod_stage_f32.hip", "rsl_math.h", "rsl_impl.h")
+# HBM bytes per RK stage of the whole batch from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# counters (scaled by a plain copy's readings); valid only for the kernel
+# sources and launch forms they were taken with
+TRAFFIC_FILES = {"ensemble": os.path.join(ROOT, "profiles", "sod_loop_ensemble_f32_traffic.txt"),
+                 "sweep": os.path.join(ROOT, "profiles", "sod_loop_sweep_f64_traffic.txt"),
+                 "scaled": os.path.join(ROOT, "profiles", "sod_loop_scaled_f64_traffic.txt")}
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--dtype", default="f64", choices=("f64", "f32"))
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--dev-steps", type=int, default=1000,
+                    help="steps taken before tuning and timing, so that the flows have developed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default stage-kernel variants")
     ap.add_argument("--variants", default=None,
                     help="comma-separated stage-kernel variant per velocity class (-1: empty), and an eighth "
                          "for the whole batch as one class (-1: per class); skips the autotuner")
-    ap.add_argument("--aux", default="all", choices=("none", "all", "c1", "bjorken", "ensemble", "scaled",
-                                                           "learned"),
-                    help="also measure the near-inviscid tube, the Bjorken batch, the uneven Sod ensemble, the "
-                         "sweep scaled out of the cache and the learned correction (all), or one of them")
+    ap.add_argument("--aux", default="all",
+                    choices=("none", "all", "sweep", "c1", "bjorken", "scaled", "learned", "learned_c5"),
+                    help="also measure the aux legs (all: every one but learned_c5), or one of them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy five times (the reference kernel for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters to bytes)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
-def build_batch(rsl, dtype):
+def _progress(msg):
+    """One line per finished part of the run, on stderr (the JSON line is stdout's only line)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ workloads
+
+def ensemble_params(n=ENS_N, seed=ENS_SEED):
+    """(nz, Q_xi, T_R, tau_r, dt) of every instance of the uneven ensemble."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        nz = int(round(np.exp(rng.uniform(np.log(256), np.log(16384)))))
+        Q = int(rng.choice((8, 16, 32, 64)))
+        TR = 1.0 / rng.uniform(1.1, 3.0)
+        tau = float(np.exp(rng.uniform(np.log(1e-4), np.log(1.0))))
+        out.append((nz, Q, TR, tau, min(0.5 / nz, 0.5 * tau)))
+    return out
+
+
+def ensemble_batch(rsl, params):
+    quads = {Q: rsl.Quadrature(QL, Q, min(Q - 1, 4)) for Q in (8, 16, 32, 64)}
+    qs, probs, dts = [], [], []
+    for nz, Q, TR, tau, dt in params:
+        qs.append(quads[Q])
+        probs.append(rsl.make_problem(nz=nz, dtype="f32", bc="outflow", tau_r=tau, nL=1.0, TL=1.0,
+                                      nR=TR ** 3, TR=TR))
+        dts.append(dt)
+    return rsl.Batch(qs, probs, dts), qs, probs
+
+
+def sweep_batch(rsl, dtype="f64", copies=1):
     quads, probs, dts = [], [], []
-    for Q in QXI:
-        quad = rsl.Quadrature(QL, Q, NOM)
-        for es in ETAS:
-            quads.append(quad)
-            probs.append(rsl.make_problem(nz=NZ, dtype=dtype, bc="outflow", tau_mode="etas",
-                                          tau_aw0=0.3854 * es, nL=1.0, TL=1.0, nR=0.4, TR=0.8))
-            dts.append(0.5 / NZ)
-    B = rsl.Batch(quads, probs, dts)
-    B.init()
-    return B
+    for Q in SWEEP_QXI:
+        quad = rsl.Quadrature(QL, Q, 4)
+        for es in SWEEP_ETAS:
+            for _ in range(copies):
+                quads.append(quad)
+                probs.append(rsl.make_problem(nz=SWEEP_NZ, dtype=dtype, bc="outflow", tau_mode="etas",
+                                              tau_aw0=TAU_AW0_PER_ETAS * es, nL=1.0, TL=1.0, nR=0.4, TR=0.8))
+                dts.append(0.5 / SWEEP_NZ)
+    return rsl.Batch(quads, probs, dts), quads, probs
 
+
+# ------------------------------------------------------------ roofline record
 
 def kernel_source_hash():
     h = hashlib.sha256()
@@ -101,25 +141,6 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, "paper_1612_01287_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
-
-
-def measured_traffic(dtype, variants):
-    """HBM bytes per stage launch group from the committed counter summary, or
-    None when it was taken on other kernel sources or variants."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    rec = {}
-    with open(TRAFFIC_FILE) as fh:
-        for line in fh:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                rec[k.strip()] = v.strip()
-    key = "bytes_per_stage_group_" + dtype
-    if rec.get("kernel_source_hash") != kernel_source_hash() or key not in rec:
-        return None
-    if rec.get("kernel_forms_" + dtype) != kernel_forms(variants):
-        return None
-    return float(rec[key])
 
 
 def kernel_forms(variants):
@@ -135,30 +156,55 @@ def kernel_forms(variants):
     return ",".join(form(v) for v in variants[:rsl.N_CLASSES])
 
 
-def kernel_roofline(torch, B, dtype, updates_per_step, variants, chunk, stream, reps=10):
-    """Average duration of one RK stage of the whole batch (a stage launch
-    group: the stage kernels of every velocity class, launched concurrently
-    from one stream), from HIP events on that stream around graph replays of
-    `chunk` steps (3 chunk stage groups each)."""
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
-    for r in range(reps):
-        ev[2 * r].record(stream)
-        B.graph_step(chunk, stream=stream)
-        ev[2 * r + 1].record(stream)
-    ev[-1].synchronize()
-    ms = sum(ev[i].elapsed_time(ev[i + 1]) for i in range(0, len(ev), 2)) / (3 * chunk * reps)
-    cell_vel = updates_per_step / 3
+def read_record(path):
+    rec = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    rec[k.strip()] = v.strip()
+    return rec
+
+
+def measured_traffic(workload, variants):
+    """HBM bytes per RK stage of the whole batch from the committed counter
+    record of `workload`, or None when it was taken on other kernel sources
+    or launch forms."""
+    rec = read_record(TRAFFIC_FILES[workload])
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if rec.get("kernel_forms") != kernel_forms(variants):
+        return None
+    return float(rec["bytes_per_stage"])
+
+
+def roofline(seconds, stages, cell_vel, dtype, workload, variants, label):
+    """HBM roofline of one RK stage of the whole batch: algorithmic bytes
+    (BYTES_PER_CELL_VEL_STEP / 3 per cell-velocity) over the mean stage time."""
+    us = seconds / stages * 1e6
     bytes_per_launch = BYTES_PER_CELL_VEL_STEP[dtype] / 3.0 * cell_vel
-    gbs = bytes_per_launch / (ms * 1e-3) / 1e9
+    gbs = bytes_per_launch / (us * 1e-6) / 1e9
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=measured_traffic(dtype, variants),
-                kernel="Sod stage launch group (one RK stage of all velocity classes; mean over %d graph-replayed "
-                       "stages)" % (3 * chunk * reps), avg_launch_us=round(ms * 1e3, 2),
-                bytes_per_launch=bytes_per_launch, variants=variants, kernel_forms=kernel_forms(variants),
-                kernel_source_hash=kernel_source_hash(),
-                residency="the sweep's three fields (%.0f MB) fit in the 256 MB last-level cache, so part of the "
-                          "traffic is served there; the HBM-resident cases are the scaled and ensemble aux legs"
-                          % (3 * BYTES_PER_CELL_VEL_STEP[dtype] / 8 * cell_vel / 1e6))
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=measured_traffic(workload, variants),
+                kernel=label, avg_launch_us=round(us, 2), bytes_per_launch=bytes_per_launch,
+                variants=variants, kernel_forms=kernel_forms(variants), kernel_source_hash=kernel_source_hash())
+
+
+def timed_replays(torch, B, chunk, nsteps, stream):
+    """Wall time and HIP-event time (launching stream) of graph replays
+    covering nsteps steps; returns (steps done, wall s, event s)."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    done = 0
+    while done < nsteps:
+        B.graph_step(chunk, stream=stream)
+        done += chunk
+    e1.record(stream)
+    e1.synchronize()
+    return done, time.perf_counter() - t0, e0.elapsed_time(e1) * 1e-3
 
 
 def _events(torch, stream, fn, reps=1):
@@ -171,9 +217,71 @@ def _events(torch, stream, fn, reps=1):
     return e0.elapsed_time(e1) * 1e-3
 
 
-def _progress(msg):
-    """One line per finished part of the run, on stderr (the JSON line is stdout's only line)."""
-    print("bench: " + msg, file=sys.stderr, flush=True)
+def _variants(rsl, B):
+    return [B.variant(c)[0] for c in range(rsl.N_CLASSES + 1)]
+
+
+def _apply_variants(rsl, B, spec):
+    for c, v in enumerate(int(x) for x in spec.split(",")):
+        if v >= 0 and (c == rsl.N_CLASSES or B.variant(c)[0] >= 0):
+            B.set_variant(c, v)
+
+
+# --------------------------------------------------------------- CPU oracle
+
+def _host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline_all_cores(params, budget_s=15.0):
+    """The oracle (plain C, one instance per thread; ctypes releases the GIL
+    during each call) on the host's cores, over the first instances of the
+    ensemble, 2 RK3 steps each from the initial state, until the budget is
+    spent: updates/s of the whole pool."""
+    import oracle
+    cores = _host_cores()
+    sets = {}
+
+    def one(i):
+        nz, Q, TR, tau, dt = params[i]
+        S = oracle.Sod(sets[Q], nz, nL=1.0, TL=1.0, nR=TR ** 3, TR=TR, tau_r=tau, bc=oracle.BC_OUTFLOW,
+                       store_f32=True)
+        S.run(S.init(), dt, 2)
+        return 3.0 * 2 * nz * 3 * Q
+
+    for Q in (8, 16, 32, 64):
+        sets[Q] = oracle.VelocitySet(QL, Q, min(Q - 1, 4))
+    t0 = time.perf_counter()
+    updates, done = 0.0, 0
+    with concurrent.futures.ThreadPoolExecutor(max_workers=cores) as pool:
+        while time.perf_counter() - t0 < budget_s and done < len(params):
+            n = min(cores, len(params) - done)
+            updates += sum(pool.map(one, range(done, done + n)))
+            done += n
+    el = time.perf_counter() - t0
+    return dict(value=updates / el, unit="updates/s", cores=cores, kind="oracle",
+                sample="2 RK3 steps from the initial state of each of the ensemble's first %d instances, one "
+                       "instance per thread on %d host threads (plain C, binary32 storage mode), %.1f s"
+                       % (done, cores, el))
+
+
+def cpu_baseline_one_core(params, budget_s=8.0):
+    import oracle
+    nz, Q, TR, tau, dt = params[0]
+    S = oracle.Sod(oracle.VelocitySet(QL, Q, min(Q - 1, 4)), nz, nL=1.0, TL=1.0, nR=TR ** 3, TR=TR, tau_r=tau,
+                   bc=oracle.BC_OUTFLOW, store_f32=True)
+    f = S.init()
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        f = S.run(f, dt, 1)
+        steps += 1
+    return dict(value=3.0 * steps * nz * 3 * Q / (time.perf_counter() - t0), unit="updates/s", cores=1,
+                kind="oracle", sample="%d RK3 steps of the ensemble's first instance (N_z = %d, V = %d), "
+                                      "single-threaded" % (steps, nz, 3 * Q))
 
 
 def _oracle_rate(fn, updates, sample):
@@ -184,15 +292,49 @@ def _oracle_rate(fn, updates, sample):
                 sample=sample)
 
 
+# ------------------------------------------------------------------ aux legs
+
+def sweep_leg(torch, rsl, stream, cpu=True, steps=2000, chunk=10):
+    """The finite-viscosity sweep, whole 2000-step run, tuned halfway through."""
+    B, quads, probs = sweep_batch(rsl, "f64")
+    B.init(stream=stream)
+    B.step(steps // 2, stream=stream)
+    B.autotune(reps=5, stream=stream)
+    B.init(stream=stream)
+    B.graph_step(chunk, stream=stream)
+    B.init(stream=stream)
+    done, wall, ev = timed_replays(torch, B, chunk, steps, stream)
+    rc, bad = B.status(stream)
+    assert rc == 0, "non-finite sweep instance %d" % bad
+    cell_vel = sum(SWEEP_NZ * q.V for q in quads)
+    variants = _variants(rsl, B)
+    roof = roofline(ev, 3 * done, cell_vel, "f64", "sweep", variants,
+                    "Sod loop-form stage kernel, whole batch, mean over %d graph-replayed stages" % (3 * done))
+    roof["residency"] = ("the three fields (%.0f MB) fit in the 256 MB last-level cache: part of the traffic is "
+                         "served there, so this is not an HBM figure" % (3 * 8 * cell_vel / 1e6))
+    out = {"workload": "Sod finite-viscosity sweep: 16 instances, N_z = 4096, Q_L = 3, Q_xi in {8,16,40,100}, "
+                       "eta/s in {0.01,0.1,1,10}, N_Omega = 4, f64, the whole 2000-step run",
+           "value": 3.0 * cell_vel * done / wall, "unit": "updates/s", "ms_per_step": wall / done * 1e3,
+           "roofline": roof}
+    if cpu:
+        import oracle
+        S = oracle.Sod(oracle.VelocitySet(QL, 100, 4), SWEEP_NZ, nL=1.0, TL=1.0, nR=0.4, TR=0.8,
+                       tau_mode=oracle.TAU_ETAS, tau_aw0=TAU_AW0_PER_ETAS * 0.1, bc=oracle.BC_OUTFLOW)
+        out["cpu_baseline"] = _oracle_rate(lambda: S.run(S.init(), 0.5 / SWEEP_NZ, 10), 3.0 * 10 * SWEEP_NZ * 300,
+                                           "10 RK3 steps of the R-SLB(4;100), eta/s = 0.1 instance "
+                                           "(single-threaded plain C)")
+    return out
+
+
 def c1_leg(torch, rsl, stream, cpu=True):
     """The near-inviscid tube: N_z = 400, R-SLB(3;8), tau_r = 1e-3, dt = 1.25e-3,
-    200 steps (launch-bound, not HBM-bound): updates/s of the whole run as a
-    one-instance batch (autotuned on a developed state) replayed from graphs
-    of 10 steps, and as eager single-instance steps.  Parity: one more batch step from the final state
-    against one oracle step from that same state; and the final state against
-    the oracle's 200-step run (the CPU baseline's sample), beside the spread
-    of the oracle itself under a one-ulp perturbation of its input (WENO5
-    without a regulariser amplifies rounding differences near the fronts)."""
+    200 steps (launch-bound): updates/s of the whole run as a one-instance
+    batch replayed from graphs of 10 steps (autotuned on a developed state),
+    and as eager single-instance steps.  Parity: one more batch step from the
+    final state against one oracle step from that state; and the final state
+    against the oracle's 200-step run, beside the spread of the oracle itself
+    under a one-ulp perturbation of its input (WENO5 without a regulariser
+    amplifies rounding differences near the fronts)."""
     import numpy as np
     import oracle
     nz, dt, steps = 400, 1.25e-3, 200
@@ -226,7 +368,7 @@ def c1_leg(torch, rsl, stream, cpu=True):
                        "dt = 1.25e-3, 200 steps, f64",
            "value": updates / sec, "unit": "updates/s", "seconds": sec,
            "eager_single_instance_updates_per_s": updates / sec_eager,
-           "variants": [B.variant(c)[0] for c in range(rsl.N_CLASSES + 1)],
+           "variants": _variants(rsl, B),
            "one_step_rel_err_vs_oracle": rel(one, S.run(got, dt, 1)),
            "run_rel_err_vs_oracle": rel(got, ref), "oracle_one_ulp_envelope": rel(pert, ref)}
     if cpu:
@@ -238,37 +380,25 @@ def c1_leg(torch, rsl, stream, cpu=True):
 def scaled_leg(torch, rsl, stream, copies=128, dev_steps=1000, steps=20, chunk=10):
     """The sweep scaled out of the last-level cache: 128 copies of each of its
     16 instances (2048 instances, 24.8 GB in the three f fields, FP64), run
-    for 1000 steps (the state the headline's variants are tuned on), tuned,
-    then 20 steps timed in graph replays of 10."""
-    quads, probs, dts = [], [], []
-    for Q in QXI:
-        quad = rsl.Quadrature(QL, Q, NOM)
-        for es in ETAS:
-            for _ in range(copies):
-                quads.append(quad)
-                probs.append(rsl.make_problem(nz=NZ, bc="outflow", tau_mode="etas", tau_aw0=0.3854 * es,
-                                              nL=1.0, TL=1.0, nR=0.4, TR=0.8))
-                dts.append(0.5 / NZ)
-    B = rsl.Batch(quads, probs, dts)
+    for 1000 steps, tuned on that state, then 20 steps timed in graph replays
+    of 10."""
+    B, quads, probs = sweep_batch(rsl, "f64", copies=copies)
     B.init(stream=stream)
     B.step(dev_steps, stream=stream)
     B.autotune(reps=3, stream=stream)
     B.graph_step(chunk, stream=stream)
-    sec = _events(torch, stream, lambda: B.graph_step(chunk, stream=stream), reps=steps // chunk)
+    done, wall, ev = timed_replays(torch, B, chunk, steps, stream)
     rc, bad = B.status(stream)
     assert rc == 0, "non-finite scaled-sweep instance %d" % bad
-    cellvel = sum(p.nz * q.V for p, q in zip(probs, quads))
-    updates = 3.0 * cellvel * steps
-    gbs = BYTES_PER_CELL_VEL_STEP["f64"] * cellvel * steps / sec / 1e9
+    cell_vel = sum(p.nz * q.V for p, q in zip(probs, quads))
+    variants = _variants(rsl, B)
+    roof = roofline(ev, 3 * done, cell_vel, "f64", "scaled", variants,
+                    "Sod loop-form stage kernel, whole batch, mean over %d graph-replayed stages" % (3 * done))
     return {"workload": "the sweep x %d copies: %d Sod instances, N_z = 4096, Q_xi in {8,16,40,100}, "
                         "eta/s in {0.01,0.1,1,10}, f64, steps %d-%d"
-                        % (copies, 16 * copies, dev_steps, dev_steps + steps),
-            "value": updates / sec, "unit": "updates/s", "ms_per_step": sec / steps * 1e3,
-            "f_bytes_per_field": 8 * cellvel,
-            "variants": [B.variant(c)[0] for c in range(rsl.N_CLASSES + 1)],
-            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4),
-                         "kernel": "Sod stage kernels of the whole batch, 64 B per cell-velocity and step"}}
+                        % (copies, 16 * copies, dev_steps, dev_steps + done),
+            "value": 3.0 * cell_vel * done / wall, "unit": "updates/s", "ms_per_step": wall / done * 1e3,
+            "f_bytes_per_field": 8 * cell_vel, "roofline": roof}
 
 
 def bjorken_leg(torch, rsl, stream, n=4096, window=1000, seed=3, cpu=True):
@@ -298,7 +428,8 @@ def bjorken_leg(torch, rsl, stream, n=4096, window=1000, seed=3, cpu=True):
            "value": updates / sec, "unit": "updates/s", "seconds": sec,
            "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(tflops / FP64_MFMA_PEAK_TFLOPS, 4),
-                        "kernel": "bj_mfma_kernel (K^P F, 2 Q_xi^2 Q_L flop per instance and stage)"}}
+                        "kernel": "bj_mfma_kernel (K^P F, 2 Q_xi^2 Q_L flop per instance and stage)",
+                        "avg_launch_us": round(sec * 1e6, 1)}}
     if cpu:
         import oracle
         sample = [(int(q.Q), p.tau_aw0) for q, p in zip(qs[:8], probs[:8])]
@@ -311,88 +442,24 @@ def bjorken_leg(torch, rsl, stream, n=4096, window=1000, seed=3, cpu=True):
     return out
 
 
-def ensemble_leg(torch, rsl, stream, n=1024, steps=200, chunk=100, seed=4, cpu=True):
-    import numpy as np
-    rng = np.random.default_rng(seed)
-    quads = {Q: rsl.Quadrature(QL, Q, min(Q - 1, 4)) for Q in (8, 16, 32, 64)}
-    qs, probs, dts = [], [], []
-    for _ in range(n):
-        nz = int(round(np.exp(rng.uniform(np.log(256), np.log(16384)))))
-        Q = int(rng.choice((8, 16, 32, 64)))
-        TR = 1.0 / rng.uniform(1.1, 3.0)
-        tau = float(np.exp(rng.uniform(np.log(1e-4), np.log(1.0))))
-        qs.append(quads[Q])
-        probs.append(rsl.make_problem(nz=nz, dtype="f32", bc="outflow", tau_r=tau, nL=1.0, TL=1.0,
-                                      nR=TR ** 3, TR=TR))
-        dts.append(min(0.5 / nz, 0.5 * tau))
-    B = rsl.Batch(qs, probs, dts)
-    B.init(stream=stream)
-    B.autotune(reps=3, stream=stream)
-    B.graph_step(chunk, stream=stream)
-    sec = _events(torch, stream, lambda: B.graph_step(chunk, stream=stream), reps=steps // chunk)
-    rc, bad = B.status(stream)
-    assert rc == 0, "non-finite ensemble instance %d" % bad
-    cellvel = sum(p.nz * q.V for p, q in zip(probs, qs))
-    updates = 3.0 * cellvel * steps
-    gbs = 32.0 * cellvel * steps / sec / 1e9
-    out = {"workload": "1024 uneven Sod instances, N_z log-uniform in [256, 16384], Q_xi in {8,16,32,64}, f32, "
-                       "graph replays of 100 steps, 200 steps",
-            "value": updates / sec, "unit": "updates/s", "ms_per_step": sec / steps * 1e3,
-            "f_bytes_per_field": 4 * cellvel,
-            "variants": [B.variant(c)[0] for c in range(rsl.N_CLASSES + 1)],
-            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4),
-                         "kernel": "Sod stage kernels of all classes, 32 B per cell-velocity and step"}}
-    if cpu:
-        import oracle
-        p0, q0 = probs[0], qs[0]
-        S = oracle.Sod(oracle.VelocitySet(QL, q0.Q, min(q0.Q - 1, 4)), p0.nz, nL=1.0, TL=1.0, nR=p0.n_R, TR=p0.T_R,
-                       tau_r=p0.tau_r, bc=oracle.BC_OUTFLOW, store_f32=True)
-        out["cpu_baseline"] = _oracle_rate(lambda: S.run(S.init(), dts[0], 5), 3.0 * 5 * p0.nz * q0.V,
-                                           "5 steps of the batch's first instance (N_z = %d, V = %d), "
-                                           "single-threaded plain C" % (p0.nz, q0.V))
-    return out
-
-
-def learned_leg(torch, stream):
+def learned_leg(torch, stream, n_runs=2048, nz_train=2048, n_inst=64, nz_eval=2048, epochs=100):
     from paper_1612_01287_amd import learned
     t0 = time.perf_counter()
-    X, T = learned.generate(n_runs=2048, nz=2048, t_snaps=(0.05, 0.1, 0.15, 0.2, 0.25), seed=5, q_lo=8, q_hi=128)
+    X, T = learned.generate(n_runs=n_runs, nz=nz_train, t_snaps=(0.05, 0.1, 0.15, 0.2, 0.25), seed=5, q_lo=8,
+                            q_hi=128)
     _progress("learned: %d training samples generated (%.1f s)" % (X.shape[0], time.perf_counter() - t0))
-    corr, hist = learned.train(X, T, epochs=100, batch=8192, lr=2e-3, seed=1, margin=0.25)
+    corr, hist = learned.train(X, T, epochs=epochs, batch=8192, lr=2e-3, seed=1, margin=0.25)
     torch.cuda.synchronize()
     prep = time.perf_counter() - t0
-    res = learned.evaluate(corr, n_inst=64, nz=2048, t_end=0.25, seed=6, q_lo=8, q_hi=128)
-    out = {"workload": "learned T^{mu nu} correction: R-SLB(4;8) + network vs R-SLB(4;128), 64 instances, "
-                       "N_z = 2048, t = 0.25 (scaled from 512 x 8192)",
-           "samples": int(X.shape[0]), "train_and_data_s": prep, "final_loss_scaled": hist[-1]}
+    del X, T
+    res = learned.evaluate(corr, n_inst=n_inst, nz=nz_eval, t_end=0.25, seed=6, q_lo=8, q_hi=128)
+    out = {"workload": "learned T^{mu nu} correction: R-SLB(4;8) + network vs R-SLB(4;128), %d instances, "
+                       "N_z = %d, t = 0.25; trained on %d paired runs at N_z = %d" % (n_inst, nz_eval, n_runs,
+                                                                                      nz_train),
+           "train_and_data_s": prep, "final_loss_scaled": hist[-1]}
     out.update(res)
-    if res["err_corrected"] is not None:
-        out["speedup_vs_plain"] = res["t_high_order_s"] / res["t_learned_s"]
+    out["speedup_vs_plain"] = res["t_high_order_s"] / res["t_learned_s"]
     return out
-
-
-def cpu_baseline(dtype, budget_s=15.0):
-    """The oracle (plain C, one thread) on a bounded sample of the same workload:
-    whole RK3 steps of the R-SLB(4;100) eta/s = 0.1 instance."""
-    import numpy as np
-    import oracle
-    vs = oracle.VelocitySet(QL, 100, NOM)
-    S = oracle.Sod(vs, NZ, nL=1.0, TL=1.0, nR=0.4, TR=0.8, tau_mode=oracle.TAU_ETAS,
-                   tau_aw0=0.3854 * 0.1, bc=oracle.BC_OUTFLOW, store_f32=(dtype == "f32"))
-    f = S.init()
-    dt = 0.5 / NZ
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        f = S.run(f, dt, 1)
-        steps += 1
-    el = time.perf_counter() - t0
-    ups = steps * 3 * NZ * vs.V / el
-    assert np.isfinite(f).all()
-    return dict(value=ups, unit="updates/s", cores=1, kind="oracle",
-                sample="%d RK3 steps of the R-SLB(4;100), Q_L = 3, N_z = 4096, eta/s = 0.1 instance "
-                       "(single-threaded plain C)" % steps)
 
 
 def copy_calibration(torch):
@@ -404,6 +471,8 @@ def copy_calibration(torch):
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_per_copy": n * 8, "copies": 5}))
 
+
+# --------------------------------------------------------------------- main
 
 def main():
     a = parse()
@@ -417,75 +486,82 @@ def main():
         copy_calibration(torch)
         return
     from paper_1612_01287_amd import rsl
-    B = build_batch(rsl, a.dtype)
+    params = ensemble_params()
+    B, qs, probs = ensemble_batch(rsl, params)
     stream = torch.cuda.Stream()          # graph replay needs an explicit stream
-    chunk = max(1, min(CHUNK, a.steps))
+    chunk = max(1, min(100, a.steps))
     with torch.cuda.stream(stream):
+        B.init(stream=stream)
+        if a.dev_steps > 0:
+            B.step(a.dev_steps, stream=stream)
         if a.variants:
-            for c, v in enumerate(int(x) for x in a.variants.split(",")):
-                if v >= 0 and (c == rsl.N_CLASSES or B.variant(c)[0] >= 0):
-                    B.set_variant(c, v)
+            _apply_variants(rsl, B, a.variants)
         elif not a.no_autotune:
-            # tuned on the state halfway through the run (the cost of a step
-            # grows as the flows develop), then back to the initial state
-            B.step(STEPS // 2, stream=stream)
-            B.autotune(reps=5, stream=stream)
-            B.init(stream=stream)
-        variants = [B.variant(c)[0] for c in range(rsl.N_CLASSES + 1)]
-        for _ in range(max(1, a.warmup // chunk)):
-            B.graph_step(chunk)           # first call captures the graph of `chunk` steps
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        done = 0
-        while done < a.steps:
-            B.graph_step(chunk)
-            done += chunk
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-    a.steps = done
-    rc, bad = B.status()
-    assert rc == 0, "non-finite state in instance %d of the benchmark run" % bad
-    updates_per_step = sum(3 * NZ * q.V for q in B.quads)
-    value = updates_per_step * a.steps / el
-    with torch.cuda.stream(stream):
-        roof = kernel_roofline(torch, B, a.dtype, updates_per_step, variants, chunk, stream)
-    _progress("sweep: %d steps in %.3f s" % (a.steps, el))
+            B.autotune(reps=3, stream=stream)      # on the developed state; f is restored after
+        variants = _variants(rsl, B)
+        for _ in range(max(1, -(-a.warmup // chunk))):
+            B.graph_step(chunk, stream=stream)     # the first call captures the graph of `chunk` steps
+        done, wall, ev = timed_replays(torch, B, chunk, a.steps, stream)
+    # instances whose flow met an unphysical cell (the scheme's own limit for
+    # strong shocks at small tau_r / dz, which the oracle reaches as well);
+    # they are counted, not hidden: every instance still does its full work
+    unphysical = sum(1 for st in B.instance_status(stream) if st != 0)
+    cell_vel = sum(p.nz * q.V for p, q in zip(probs, qs))
+    updates_per_step = 3 * cell_vel
+    roof = roofline(ev, 3 * done, cell_vel, "f32", "ensemble", variants,
+                    "Sod loop-form stage kernel over the whole batch (one launch per RK stage, plus the "
+                    "per-cell kernel at the first stage of each replay); mean over the %d timed stages"
+                    % (3 * done))
+    roof["residency"] = "the three binary32 fields (%.2f GB) are HBM-resident" % (3 * 4 * cell_vel / 1e9)
+    _progress("ensemble: %d steps in %.3f s (%.3f s on the stream's events)" % (done, wall, ev))
     out = {
         "metric": "distribution updates/s (cells x velocities x RK stages)",
-        "value": value,
+        "value": updates_per_step * done / wall,
         "unit": "updates/s",
         "n_gpus": 1,
-        "steps": a.steps,
+        "steps": done,
         "warmup": a.warmup,
-        "ms_per_step": el / a.steps * 1e3,
+        "ms_per_step": wall / done * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": a.dtype,
+        "dtype": "f32",
+        "dtype_note": "f stored in binary32 with binary32 stencil, relaxation and RK arithmetic; moments, "
+                      "Landau frame, tau and f^eq coefficients in binary64",
         "data": "synthetic (Sod initial states, seeded parameters)",
-        "config": {"workload": "Sod shock tube at finite viscosity, N_z = 4096, Q_L = 3, "
-                               "Q_xi in {8,16,40,100}, eta/s in {0.01,0.1,1,10}, N_Omega = 4, 16 instances",
+        "config": {"workload": "uneven Sod ensemble: 1024 instances (seed 4), N_z log-uniform in [256, 16384], "
+                               "Q_xi in {8,16,32,64}, Q_L = 3, N_Omega = min(Q_xi - 1, 4), T_L/T_R uniform in "
+                               "[1.1, 3], n_R = T_R^3, tau_r log-uniform in [1e-4, 1], dt = min(0.5/N_z, tau_r/2), "
+                               "outflow ghosts, f32",
                    "updates_per_step": updates_per_step, "graph_steps": chunk,
+                   "timed_from_step": a.dev_steps + max(1, -(-a.warmup // chunk)) * chunk,
+                   "instances_with_unphysical_cells": unphysical,
                    "parallelism": "single GPU"},
         "roofline": roof,
     }
     if a.aux != "none":
         cpu = not a.no_cpu_baseline
-        legs = {"c1": lambda: c1_leg(torch, rsl, stream, cpu),
+        legs = {"sweep": lambda: sweep_leg(torch, rsl, stream, cpu),
+                "c1": lambda: c1_leg(torch, rsl, stream, cpu),
                 "bjorken": lambda: bjorken_leg(torch, rsl, stream, cpu=cpu),
-                "ensemble": lambda: ensemble_leg(torch, rsl, stream, cpu=cpu),
                 "scaled": lambda: scaled_leg(torch, rsl, stream),
-                "learned": lambda: learned_leg(torch, stream)}
+                "learned": lambda: learned_leg(torch, stream),
+                "learned_c5": lambda: learned_leg(torch, stream, n_runs=1024, nz_train=8192, n_inst=512,
+                                                  nz_eval=8192, epochs=60)}
+        del B
+        torch.cuda.empty_cache()
         out["aux"] = {}
         with torch.cuda.stream(stream):
             for k, fn in legs.items():
-                if a.aux in ("all", k):
+                if a.aux == k or (a.aux == "all" and k != "learned_c5"):
                     t0 = time.perf_counter()
                     out["aux"][k] = fn()
+                    torch.cuda.empty_cache()
                     _progress("aux leg %s done (%.1f s)" % (k, time.perf_counter() - t0))
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.dtype)
-        _progress("oracle baseline done")
+        out["cpu_baseline"] = cpu_baseline_all_cores(params)
+        out["cpu_baseline_one_core"] = cpu_baseline_one_core(params)
+        _progress("oracle baselines done")
     print(json.dumps(out))
 
 

@@ -96,7 +96,10 @@ typedef struct rsl_problem {
     double tau_r;             /* RSL_TAU_CONST relaxation time                          */
     double tau_aw0;           /* RSL_TAU_ETAS: tau_{A-W;0}                              */
     double lambda_ref;        /* RSL_TAU_ETAS: lambda_ref (1 in the paper's setups)     */
-    double kappa;             /* stiffness guard dt <= kappa * tau_min (0 -> 2.0)       */
+    double kappa;             /* stiffness guard: dt gamma (1 + |beta|) / tau_AW <= kappa
+                                 at the states of the inviscid Riemann solution (the
+                                 initial states and the two plateaus, Sec. IV B 1);
+                                 0 -> 2.0 (RK3 is stable on the real axis to 2.51)  */
 } rsl_problem;
 
 /* Build the velocity set R-SLB(N_Omega; Q_xi) with Q_L radial nodes
@@ -127,6 +130,14 @@ int rsl_quad_table(const rsl_quad* q, int which, double* host_out, int n, int* c
 /* Elements per velocity plane for nz cells (multiple of 64, >= nz). */
 int rsl_pitch(int nz);
 
+/* Limits of the time step that rsl_step's guards apply (host only, no device
+ * work; q may be RSL_QUAD_HOST_ONLY): dt must be < *cfl_dt (dt max|xi|/dz < 1,
+ * Sec. III F) and <= *stiff_dt (kappa over the largest relaxation rate
+ * gamma (1 + |beta|) / tau_AW at the states of the inviscid Riemann solution,
+ * Sec. IV B 1; eq. L_Sod).  HUGE_VAL where no bound applies (no advection in
+ * Bjorken flow, tau = infinity).  RSL_EINVAL for NULL pointers or a bad problem. */
+int rsl_max_dt(const rsl_quad* q, const rsl_problem* p, double* cfl_dt, double* stiff_dt);
+
 /* Sizes of the caller-owned buffers for one instance: f (the state) and work
  * (two RK stage copies of f, the boundary states and a status word). */
 int rsl_sizes(const rsl_quad* q, const rsl_problem* p, size_t* f_bytes, size_t* work_bytes);
@@ -144,15 +155,24 @@ int rsl_init(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_de
  * Anderson-Witting term) or L_Bjorken (eq. L_Bjorken).  *t (host) is the
  * time (Sod) or proper time tau (Bjorken) and advances by nsteps*dt.
  * Errors: RSL_EINVAL; RSL_EUNSTABLE if dt*max|xi|/dz >= 1 (CFL, eq. CFL) or
- * dt > kappa * tau_min at the initial states, unless RSL_FLAG_FORCE_UNSTABLE.
+ * dt gamma (1 + |beta|) / tau_AW > kappa at a state of the inviscid Riemann
+ * solution (see rsl_problem.kappa), unless RSL_FLAG_FORCE_UNSTABLE.
  * Unphysical cell states are reported by the next rsl_moments / rsl_status. */
 int rsl_step(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_dev,
              double* t, double dt, int nsteps, void* hip_stream);
 
-/* Per-cell fields (RSL_NMOM doubles per cell, cell-major: out[s*13 + field])
- * written to out_dev on the stream.  Bjorken writes one row. */
+/* Per-cell fields written to out_dev on the stream, cell-major:
+ * out[s*fields + field], in the order listed at RSL_NMOM.  fields is
+ * RSL_MOM_RAW5 (the five moments of eq. macro_jk) or RSL_MOM_ALL (those and the
+ * derived fields; the derived ones are NaN in a cell whose Landau frame does
+ * not exist, which also sets the status word).  Bjorken writes one row.
+ * Stream-ordered and asynchronous like rsl_step (so it can be captured in a
+ * graph); an unphysical or non-finite state met by earlier calls is reported
+ * by rsl_status, which synchronises.  RSL_EINVAL for other fields values. */
+#define RSL_MOM_RAW5  5
+#define RSL_MOM_ALL   13   /* = RSL_NMOM */
 int rsl_moments(const rsl_quad* q, const rsl_problem* p, const void* f_dev, void* work_dev,
-                double* out_dev, void* hip_stream);
+                double* out_dev, int fields, void* hip_stream);
 
 /* Synchronises the stream and reads the status word: RSL_OK, or
  * RSL_ENONFINITE if any kernel since rsl_init met an unphysical state. */
@@ -201,8 +221,10 @@ int rsl_batch_graph_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, 
  * field s (stage 3 writes f_{n+1} over f_n).  For custom drivers and timing. */
 int rsl_batch_stage(rsl_batch* b, void* f_dev, void* work_dev, int stage, void* hip_stream);
 /* Per-cell fields of every instance, rows concatenated in instance order
- * (nz rows per Sod instance, one per Bjorken instance), RSL_NMOM per row. */
-int rsl_batch_moments(rsl_batch* b, const void* f_dev, void* work_dev, double* out_dev, void* hip_stream);
+ * (nz rows per Sod instance, one per Bjorken instance), `fields` per row
+ * (RSL_MOM_RAW5 or RSL_MOM_ALL, as for rsl_moments). */
+int rsl_batch_moments(rsl_batch* b, const void* f_dev, void* work_dev, double* out_dev, int fields,
+                      void* hip_stream);
 /* Kernel path of a Bjorken batch: -1 automatic (matrix cores when every
  * instance fits: Q_L <= 4 and a padded Q_xi x 16 Q_L stage field within the
  * LDS), 0 one workgroup per instance on the vector units, 1 matrix cores
@@ -262,6 +284,11 @@ int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void
 /* Synchronises and reads every instance's status word; *first_bad (if not
  * NULL) receives the first failing instance or -1. */
 int rsl_batch_status(rsl_batch* b, void* work_dev, void* hip_stream, int* first_bad);
+/* Synchronises and writes every instance's status to status[0..n-1]
+ * (RSL_OK or RSL_ENONFINITE), so that a failing instance can be told from the
+ * others of its launch group.  RSL_EINVAL for NULL arguments, RSL_EDEVICE on
+ * a HIP error. */
+int rsl_batch_instance_status(rsl_batch* b, void* work_dev, void* hip_stream, int* status);
 
 /* ------------------------------------------------ learned T^{mu nu} correction
  * Not part of the paper: a per-cell network that maps the local moments of a

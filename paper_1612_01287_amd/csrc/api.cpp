@@ -78,28 +78,86 @@ InstDesc make_desc(const rsl_quad* q, const rsl_problem* p, void* f, void* work,
     return d;
 }
 
+// Plateau of the inviscid Riemann problem between two ideal gases at rest with
+// P = E/3 (Sec. IV B 1): P_C is the root of eq. Sod:PC, beta_C follows from eq.
+// Sod:uplateau, n_I from eq. Sod:nI and n_II from eq. Sod:nII.  The
+// higher-pressure side plays the left state (the problem mirrors otherwise);
+// equal pressures give no flow.
+RiemannPlateau riemann_plateau(double nL, double PL, double nR, double PR) {
+    RiemannPlateau r{};
+    const bool mirror = PR > PL;
+    if (mirror) {
+        std::swap(nL, nR);
+        std::swap(PL, PR);
+    }
+    if (!(PL > PR)) {
+        r.PC = PL;
+        r.betaC = 0.0;
+        r.nI = nL;
+        r.nII = nR;
+    } else {
+        const double h = std::sqrt(3.0) / 2.0;
+        auto resid = [&](double P) {
+            const double a = std::pow(PL / P, h);
+            const double d = P - PR;
+            return (a - 1.0) / (a + 1.0) - std::sqrt(3.0 * d * d / ((P + 3.0 * PR) * (3.0 * P + PR)));
+        };
+        double lo = PR, hi = PL;      // resid(PR) > 0 > resid(PL)
+        for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            (resid(mid) > 0.0 ? lo : hi) = mid;
+        }
+        const double PC = 0.5 * (lo + hi), d = PC - PR;
+        r.PC = PC;
+        r.betaC = std::sqrt(3.0 * d * d / ((PC + 3.0 * PR) * (3.0 * PC + PR)));
+        r.nI = nL * std::pow(PC / PL, 0.75);
+        r.nII = nR * std::sqrt(PC * (PR + 3.0 * PC) / (PR * (PC + 3.0 * PR)));
+    }
+    if (mirror) {
+        std::swap(r.nI, r.nII);
+        r.betaC = -r.betaC;
+    }
+    return r;
+}
+
+// Largest dt allowed by the CFL condition (dt max|xi| / dz < 1, Sec. III F)
+// and by the stiffness of the AW term, whose rate for population j is
+// gamma (1 - beta xi_j) / tau <= gamma (1 + |beta|) / tau.  The largest rate
+// over the flow is taken over the states of the inviscid Riemann solution
+// (the two initial states and the two plateaus, whose speed |beta_C| is the
+// largest in the flow); Bjorken flow is at rest.  Infinite where no bound
+// applies.
+void stability_limits(const rsl_quad* q, const rsl_problem* p, double* cfl_dt, double* stiff_dt) {
+    *cfl_dt = *stiff_dt = HUGE_VAL;
+    if (p->problem == RSL_SOD) *cfl_dt = (p->z_hi - p->z_lo) / p->nz / std::fabs(q->xi.back());
+    if (p->tau_mode == RSL_TAU_INF) return;
+    const double kappa = p->kappa > 0 ? p->kappa : kDefaultKappa;
+    const double lref = p->lambda_ref > 0 ? p->lambda_ref : 1.0;
+    auto tau_of = [&](double n, double T) {
+        if (p->tau_mode == RSL_TAU_CONST) return p->tau_r;
+        return p->tau_aw0 / T * (1.0 - 0.25 * std::log(n / (T * T * T) * lref));
+    };
+    double rate = 1.0 / tau_of(p->n_L, p->T_L);
+    if (p->problem == RSL_SOD) {
+        const RiemannPlateau r = riemann_plateau(p->n_L, p->n_L * p->T_L, p->n_R, p->n_R * p->T_R);
+        const double b = std::fabs(r.betaC);
+        const double speed = std::sqrt((1.0 + b) / (1.0 - b));     // gamma (1 + |beta|)
+        rate = std::max(rate, 1.0 / tau_of(p->n_R, p->T_R));
+        rate = std::max(rate, speed / tau_of(r.nI, r.PC / r.nI));
+        rate = std::max(rate, speed / tau_of(r.nII, r.PC / r.nII));
+    }
+    *stiff_dt = rate > 0.0 ? kappa / rate : 0.0;    // a non-positive tau leaves no stable step
+}
+
 int check_stability(const rsl_quad* q, const rsl_problem* p, double dt) {
     if (!(dt > 0.0 && std::isfinite(dt))) return set_error(RSL_EINVAL, "dt must be > 0");
-    const double kappa = p->kappa > 0 ? p->kappa : 2.0;
-    const bool force = p->flags & RSL_FLAG_FORCE_UNSTABLE;
-    if (p->problem == RSL_SOD) {
-        const double dz = (p->z_hi - p->z_lo) / p->nz;
-        const double vmax = std::fabs(q->xi.back());
-        if (dt * vmax / dz >= 1.0 && !force)
-            return set_error(RSL_EUNSTABLE, "CFL number dt*max|xi|/dz >= 1");
-    }
-    if (p->tau_mode != RSL_TAU_INF && !force) {
-        double tmin = p->tau_r;
-        if (p->tau_mode == RSL_TAU_ETAS) {
-            auto tau_of = [&](double n, double T) {
-                return p->tau_aw0 / T * (1.0 - 0.25 * std::log(n / (T * T * T) * (p->lambda_ref > 0 ? p->lambda_ref : 1.0)));
-            };
-            tmin = tau_of(p->n_L, p->T_L);
-            if (p->problem == RSL_SOD) tmin = std::min(tmin, tau_of(p->n_R, p->T_R));
-        }
-        if (!(dt <= kappa * tmin))
-            return set_error(RSL_EUNSTABLE, "dt exceeds kappa * tau_AW (stiff relaxation); set RSL_FLAG_FORCE_UNSTABLE to override");
-    }
+    if (p->flags & RSL_FLAG_FORCE_UNSTABLE) return RSL_OK;
+    double cfl_dt, stiff_dt;
+    stability_limits(q, p, &cfl_dt, &stiff_dt);
+    if (!(dt < cfl_dt)) return set_error(RSL_EUNSTABLE, "CFL number dt*max|xi|/dz >= 1");
+    if (!(dt <= stiff_dt))
+        return set_error(RSL_EUNSTABLE, "dt * gamma (1 + |beta|) / tau_AW exceeds kappa (stiff relaxation); set "
+                                        "RSL_FLAG_FORCE_UNSTABLE to override");
     return RSL_OK;
 }
 
@@ -266,6 +324,14 @@ int rsl_quad_table(const rsl_quad* q, int which, double* host_out, int n, int* c
     return RSL_OK;
 }
 
+int rsl_max_dt(const rsl_quad* q, const rsl_problem* p, double* cfl_dt, double* stiff_dt) {
+    if (!q || !cfl_dt || !stiff_dt) return set_error(RSL_EINVAL, "null argument");
+    int rc = check_problem(q, p);
+    if (rc) return rc;
+    stability_limits(q, p, cfl_dt, stiff_dt);
+    return RSL_OK;
+}
+
 int rsl_sizes(const rsl_quad* q, const rsl_problem* p, size_t* f_bytes, size_t* work_bytes) {
     if (!q) return set_error(RSL_EINVAL, "null rsl_quad");
     int rc = check_problem(q, p);
@@ -312,13 +378,14 @@ int rsl_step(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_de
 }
 
 int rsl_moments(const rsl_quad* q, const rsl_problem* p, const void* f_dev, void* work_dev, double* out_dev,
-                void* hip_stream) {
+                int fields, void* hip_stream) {
     int rc = check_quad(q);
     if (rc || (rc = check_problem(q, p))) return rc;
     if (!f_dev || !work_dev || !out_dev) return set_error(RSL_EINVAL, "null device buffer");
+    if (fields != RSL_MOM_RAW5 && fields != RSL_MOM_ALL) return set_error(RSL_EINVAL, "fields must be RSL_MOM_RAW5 or RSL_MOM_ALL");
     InstDesc d = make_desc(q, p, (void*)f_dev, work_dev, 0.0);
-    if (p->problem == RSL_SOD) return launch_sod_moments(d, f_dev, out_dev, (hipStream_t)hip_stream);
-    return launch_bj_moments(d, f_dev, out_dev, (hipStream_t)hip_stream);
+    if (p->problem == RSL_SOD) return launch_sod_moments(d, f_dev, out_dev, fields, (hipStream_t)hip_stream);
+    return launch_bj_moments(d, f_dev, out_dev, fields, (hipStream_t)hip_stream);
 }
 
 int rsl_status(const rsl_quad* q, const rsl_problem* p, void* work_dev, void* hip_stream) {

@@ -541,12 +541,13 @@ int rsl_batch_graph_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, 
     return RSL_OK;
 }
 
-int rsl_batch_moments(rsl_batch* b, const void* f_dev, void* work_dev, double* out_dev, void* hip_stream) {
+int rsl_batch_moments(rsl_batch* b, const void* f_dev, void* work_dev, double* out_dev, int fields,
+                      void* hip_stream) {
     if (!b || !f_dev || !work_dev || !out_dev) return set_error(RSL_EINVAL, "null argument");
     size_t row = 0;
     for (int i = 0; i < b->n; ++i) {
         int rc = rsl_moments(b->quads[i], &b->probs[i], (const char*)f_dev + b->f_off[i],
-                             (char*)work_dev + b->w_off[i], out_dev + row * RSL_NMOM, hip_stream);
+                             (char*)work_dev + b->w_off[i], out_dev + row * fields, fields, hip_stream);
         if (rc) return rc;
         row += b->probs[i].problem == RSL_SOD ? b->probs[i].nz : 1;
     }
@@ -740,6 +741,16 @@ int rsl_batch_status(rsl_batch* b, void* work_dev, void* hip_stream, int* first_
             if (first_bad) *first_bad = i;
             return rc;
         }
+    }
+    return RSL_OK;
+}
+
+int rsl_batch_instance_status(rsl_batch* b, void* work_dev, void* hip_stream, int* status) {
+    if (!b || !work_dev || !status) return set_error(RSL_EINVAL, "null argument");
+    for (int i = 0; i < b->n; ++i) {
+        const int rc = rsl_status(b->quads[i], &b->probs[i], (char*)work_dev + b->w_off[i], hip_stream);
+        if (rc != RSL_OK && rc != RSL_ENONFINITE) return rc;
+        status[i] = rc;
     }
     return RSL_OK;
 }

@@ -156,7 +156,7 @@ __global__ void bj_init_kernel(InstDesc d, double n0, double T, double tau0) {
 }
 
 template <typename Tf>
-__global__ void bj_moments_kernel(InstDesc d, const Tf* f, double* out) {
+__global__ void bj_moments_kernel(InstDesc d, const Tf* f, double* out, int nf) {
     __shared__ double red[3 * kBjBlock];
     __shared__ double fs[4096];
     for (int v = threadIdx.x; v < d.V; v += blockDim.x) fs[v] = (double)f[v];
@@ -166,9 +166,8 @@ __global__ void bj_moments_kernel(InstDesc d, const Tf* f, double* out) {
     if (threadIdx.x == 0) {
         const double P = E / 3.0;
         const double T = d.gas == RSL_GAS_IDEAL ? P / n : sqrt(sqrt(P));
-        out[0] = n; out[1] = 0.0; out[2] = E; out[3] = 0.0; out[4] = PL;
-        out[5] = n; out[6] = E; out[7] = P; out[8] = T; out[9] = 0.0;
-        out[10] = n / (T * T * T); out[11] = 0.0; out[12] = PL - P;
+        const double row[RSL_NMOM] = {n, 0.0, E, 0.0, PL, n, E, P, T, 0.0, n / (T * T * T), 0.0, PL - P};
+        for (int q = 0; q < nf; ++q) out[q] = row[q];
     }
 }
 
@@ -216,12 +215,12 @@ int launch_bj_batch_steps(const InstDesc* descs, int n, size_t lds, int dtype, c
 
 size_t bj_lds_bytes(int V) { return sizeof(double) * (4 * (size_t)V + 3 * kBjBlock); }
 
-int launch_bj_moments(const InstDesc& d, const void* f, double* out, hipStream_t s) {
+int launch_bj_moments(const InstDesc& d, const void* f, double* out, int nf, hipStream_t s) {
     if (d.V > 4096) return set_error(RSL_EUNSUPPORTED, "Bjorken moments: more than 4096 velocities");
     if (d.dtype == RSL_F64)
-        hipLaunchKernelGGL(bj_moments_kernel<double>, dim3(1), dim3(kBjBlock), 0, s, d, (const double*)f, out);
+        hipLaunchKernelGGL(bj_moments_kernel<double>, dim3(1), dim3(kBjBlock), 0, s, d, (const double*)f, out, nf);
     else
-        hipLaunchKernelGGL(bj_moments_kernel<float>, dim3(1), dim3(kBjBlock), 0, s, d, (const float*)f, out);
+        hipLaunchKernelGGL(bj_moments_kernel<float>, dim3(1), dim3(kBjBlock), 0, s, d, (const float*)f, out, nf);
     return hip_check(hipGetLastError(), "bj_moments_kernel launch");
 }
 

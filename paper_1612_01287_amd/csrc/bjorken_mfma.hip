@@ -132,9 +132,12 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
     const int nct = __builtin_amdgcn_readfirstlane((nlive * QL + 15) / 16);
     double* P = X + (size_t)Qp * NC;          // per instance: itaw, neq, th1, clock, dt, tau mode, gas,
                                               // tau_r, tau_aw0, lambda_ref, T0, 1 / stage time (12 x 16)
+    // status bits of each instance (bit 0: unphysical state met by its
+    // closure; bit 1: a non-finite population written back), one word each
+    unsigned* flag = (unsigned*)(P + 12 * kGI);
     // velocity-set tables read by the epilogue (from LDS, so that the
     // compiler does not keep per-element copies in registers across steps)
-    double* Tx2 = P + 12 * kGI;               // [Qp]      xi_j^2
+    double* Tx2 = P + 13 * kGI;               // [Qp]      xi_j^2
     double* Tw = Tx2 + Qp;                    // [QL][Qp]  w_j w_k / 4
     double* TL1 = Tw + (size_t)QL * Qp;       // [QL]      L_1(pbar_k)
     double* TKL = TL1 + QL;                   // [QL][QL]  K^L
@@ -183,8 +186,8 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
     }
 
     const double* KPt = d0.tab.KPt;
-    unsigned bad = 0;
     if (threadIdx.x < kGI) {
+        flag[threadIdx.x] = 0u;
         const int i = threadIdx.x;
         const bool live = gi[i] >= 0;
         const InstDesc& d = descs[live ? gi[i] : gi[0]];
@@ -220,6 +223,7 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
                 }
                 if (sub == 0) {
                     double itaw = 0.0, neq = 0.0, th1 = 0.0;
+                    unsigned bad = 0;
                     if (gi[i] >= 0) {
                         // the instance's parameters, staged in LDS at the start
                         const int mode = (int)P[5 * kGI + i], gas = (int)P[6 * kGI + i];
@@ -245,6 +249,7 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
                         }
                         th1 = 1.0 - T / T0;
                     }
+                    if (bad) flag[i] |= bad;   // only this thread writes instance i's word here
                     P[0 * kGI + i] = itaw;
                     P[1 * kGI + i] = neq;
                     P[2 * kGI + i] = th1;
@@ -320,15 +325,19 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
         InstDesc d = descs[gi[i]];
         rebase(d, fbase, wbase);
         Tf* f = (Tf*)d.f;
+        int nonfinite = 0;
         for (int e = threadIdx.x; e < QL * Q; e += blockDim.x) {
             const int k = e / Q, j = e - k * Q;
             const double v = X[j * NC + i * QL + k];
-            if (!isfinite(v)) bad |= 2u;
+            if (!isfinite(v)) nonfinite = 1;
             f[e] = (Tf)v;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) *d.clock = P[3 * kGI + i] + nsteps * d.dt;
-        if (bad) atomicOr(d.status, bad);
+        // this instance's flags only: its closure's word and its own populations
+        const unsigned bad = flag[i] | (__syncthreads_or(nonfinite) ? 2u : 0u);
+        if (threadIdx.x == 0) {
+            *d.clock = P[3 * kGI + i] + nsteps * d.dt;
+            if (bad) atomicOr(d.status, bad);
+        }
     }
 }
 
@@ -336,7 +345,7 @@ __global__ void __launch_bounds__(kBW * 64) bj_mfma_kernel(const InstDesc* __res
 
 size_t bj_mfma_lds_bytes(int Q, int QL) {
     const size_t Qp = (size_t)(Q + 15) / 16 * 16;
-    return sizeof(double) * (Qp * kGI * QL + 12 * kGI + Qp * (1 + QL) + 2 * QL + QL * QL);
+    return sizeof(double) * (Qp * kGI * QL + 13 * kGI + Qp * (1 + QL) + 2 * QL + QL * QL);
 }
 
 bool bj_mfma_fits(int Q, int QL) {

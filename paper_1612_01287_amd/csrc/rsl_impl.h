@@ -141,6 +141,15 @@ InstDesc make_desc(const rsl_quad* q, const rsl_problem* p, void* f, void* work,
 // CFL and relaxation-stiffness guards of one step of size dt (RSL_EUNSTABLE
 // unless RSL_FLAG_FORCE_UNSTABLE is set).
 int check_stability(const rsl_quad* q, const rsl_problem* p, double dt);
+// Default bound on dt gamma (1 + |beta|) / tau_AW: the explicit RK3 scheme is
+// stable on the negative real axis up to 2.51.
+constexpr double kDefaultKappa = 2.0;
+// Plateau of the inviscid Riemann problem of two ideal gases at rest
+// (pressure, signed velocity, densities left and right of the contact).
+struct RiemannPlateau {
+    double PC, betaC, nI, nII;
+};
+RiemannPlateau riemann_plateau(double nL, double PL, double nR, double PR);
 
 // Kernel launchers (sod.hip, bjorken.hip).
 int launch_boundary_states(const InstDesc& d, double nL, double TL, double nR, double TR,
@@ -149,7 +158,7 @@ int launch_sod_init(const InstDesc& d, hipStream_t s);
 // `seq`: the stage's index within a call (0: the first, where the loop form
 // computes the stage field's coefficients with the per-cell kernel first).
 int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s, int seq);
-int launch_sod_moments(const InstDesc& d, const void* f, double* out, hipStream_t s);
+int launch_sod_moments(const InstDesc& d, const void* f, double* out, int nf, hipStream_t s);
 int launch_sod_class_stage(const StageClass& cl, int dtype, int stage, char* fbase, char* wbase, hipStream_t s,
                            int seq);
 int stage_class_of(int V);
@@ -169,6 +178,6 @@ bool bj_mfma_fits(int Q, int QL);
 int launch_bj_mfma(const InstDesc* descs, const int* groups, int ngroups, int QL, size_t lds, int dtype, char* fbase,
                    char* wbase, int nsteps, hipStream_t s);
 int launch_bj_steps(const InstDesc& d, double tau0, double dtau, int nsteps, hipStream_t s);
-int launch_bj_moments(const InstDesc& d, const void* f, double* out, hipStream_t s);
+int launch_bj_moments(const InstDesc& d, const void* f, double* out, int nf, hipStream_t s);
 
 }  // namespace rsl

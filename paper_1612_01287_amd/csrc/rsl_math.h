@@ -211,4 +211,34 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
     return (v1 * q1 + v2 * q2 + v3 * q3) / (v1 + v2 + v3);
 }
 
+// The same flux in binary32, for populations stored in binary32.  The
+// weights are formed as ratios, w_q ~ delta_q (sigma_min / sigma_q)^2 in
+// [0, delta_q], which neither overflow nor underflow whatever the scale of
+// the populations (delta_q / sigma_q^2 itself overflows binary32 for smooth
+// data); equal indicators give exactly the ideal weights.  Stencils with a
+// vanishing or denormal-range indicator are rare outside flat regions: all
+// equal (flat data) takes the ideal weights here, the other limiting cases
+// go through the binary64 flux above.
+__device__ __forceinline__ float weno5(float a, float b, float c, float d, float e) {
+    const float q1 = (2.0f * a - 7.0f * b + 11.0f * c) * (1.0f / 6.0f);
+    const float q2 = (-b + 5.0f * c + 2.0f * d) * (1.0f / 6.0f);
+    const float q3 = (2.0f * c + 5.0f * d - e) * (1.0f / 6.0f);
+    const float r1 = a - 2.0f * b + c, t1 = a - 4.0f * b + 3.0f * c;
+    const float r2 = b - 2.0f * c + d, t2 = b - d;
+    const float r3 = c - 2.0f * d + e, t3 = 3.0f * c - 4.0f * d + e;
+    const float s1 = (13.0f / 12.0f) * r1 * r1 + 0.25f * t1 * t1;
+    const float s2 = (13.0f / 12.0f) * r2 * r2 + 0.25f * t2 * t2;
+    const float s3 = (13.0f / 12.0f) * r3 * r3 + 0.25f * t3 * t3;
+    const float sm = fminf(s1, fminf(s2, s3));
+    if (sm > 1e-30f) {
+        const float g1 = sm * __builtin_amdgcn_rcpf(s1);
+        const float g2 = sm * __builtin_amdgcn_rcpf(s2);
+        const float g3 = sm * __builtin_amdgcn_rcpf(s3);
+        const float v1 = 0.1f * g1 * g1, v2 = 0.6f * g2 * g2, v3 = 0.3f * g3 * g3;
+        return (v1 * q1 + v2 * q2 + v3 * q3) * __builtin_amdgcn_rcpf(v1 + v2 + v3);
+    }
+    if (s1 == s2 && s2 == s3) return 0.1f * q1 + 0.6f * q2 + 0.3f * q3;   // case (i), incl. all zero
+    return (float)weno5((double)a, (double)b, (double)c, (double)d, (double)e);
+}
+
 }  // namespace rsl

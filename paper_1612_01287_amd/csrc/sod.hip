@@ -40,8 +40,9 @@ __global__ void boundary_state_kernel(InstDesc d, double nL, double TL, double n
     }
 }
 
+// nf = 5: the raw moments only; nf = RSL_NMOM: raw and derived fields.
 template <typename Tf>
-__global__ void sod_moments_kernel(InstDesc d, const Tf* __restrict__ f, double* __restrict__ out) {
+__global__ void sod_moments_kernel(InstDesc d, const Tf* __restrict__ f, double* __restrict__ out, int nf) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= d.nz) return;
     double M[5] = {0, 0, 0, 0, 0};
@@ -55,8 +56,9 @@ __global__ void sod_moments_kernel(InstDesc d, const Tf* __restrict__ f, double*
         M[3] += x * pv;
         M[4] += x * x * pv;
     }
-    double* o = out + (size_t)s * RSL_NMOM;
+    double* o = out + (size_t)s * nf;
     for (int q = 0; q < 5; ++q) o[q] = M[q];
+    if (nf == 5) return;
     const CellState cs = landau(M[0], M[1], M[2], M[3], M[4]);
     if (!cs.ok) {
         for (int q = 5; q < RSL_NMOM; ++q) o[q] = NAN;
@@ -89,12 +91,12 @@ int launch_sod_init(const InstDesc& d, hipStream_t s) {
     return hip_check(hipGetLastError(), "sod_fill_kernel launch");
 }
 
-int launch_sod_moments(const InstDesc& d, const void* f, double* out, hipStream_t s) {
+int launch_sod_moments(const InstDesc& d, const void* f, double* out, int nf, hipStream_t s) {
     dim3 grid((d.nz + 127) / 128);
     if (d.dtype == RSL_F64)
-        hipLaunchKernelGGL(sod_moments_kernel<double>, grid, dim3(128), 0, s, d, (const double*)f, out);
+        hipLaunchKernelGGL(sod_moments_kernel<double>, grid, dim3(128), 0, s, d, (const double*)f, out, nf);
     else
-        hipLaunchKernelGGL(sod_moments_kernel<float>, grid, dim3(128), 0, s, d, (const float*)f, out);
+        hipLaunchKernelGGL(sod_moments_kernel<float>, grid, dim3(128), 0, s, d, (const float*)f, out, nf);
     return hip_check(hipGetLastError(), "sod_moments_kernel launch");
 }
 

@@ -181,6 +181,9 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
     }
 
     const bool out_lane = !ghost && lane >= 1;
+    // stencil arithmetic in the storage type (per-cell coefficients stay binary64)
+    using Tc = Tf;
+    const Tc dtc = (Tc)dt, dzic = (Tc)dzi, cAc = (Tc)cA, cBc = (Tc)cB;
     unsigned bad = 0;
 #pragma unroll
     for (int i0 = 0; i0 < NV; i0 += G) {
@@ -210,15 +213,16 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
                 const __attribute__((address_space(4))) double* vr =
                     (const __attribute__((address_space(4))) double*)d.tab.vrec + (size_t)v * kVrec;
                 const double x = vr[0];
+                const Tc xc = (Tc)x;
                 const Tf* wb = win + (i - i0) * WN;
-                double sv[6];
+                Tc sv[6];
 #pragma unroll
-                for (int q = 0; q < 6; ++q) sv[q] = (double)wb[lane + q];
-                double F = 0.0;
-                if (x > 0.0) F = x * weno5(sv[0], sv[1], sv[2], sv[3], sv[4]);
-                else if (x < 0.0) F = x * weno5(sv[5], sv[4], sv[3], sv[2], sv[1]);
-                const double Fm = shift_up(F);
-                double y = (double)(Tf)(sv[2] + dt * (-(F - Fm) * dzi));
+                for (int q = 0; q < 6; ++q) sv[q] = wb[lane + q];
+                Tc F = 0;
+                if (x > 0.0) F = xc * weno5(sv[0], sv[1], sv[2], sv[3], sv[4]);
+                else if (x < 0.0) F = xc * weno5(sv[5], sv[4], sv[3], sv[2], sv[1]);
+                const Tc Fm = shift_up(F);
+                Tc y = sv[2] + dtc * (-(F - Fm) * dzic);
                 if (collide) {
                     const double l1 = vr[2], wx = vr[3];
                     double gsum = 0.0;
@@ -227,15 +231,15 @@ __device__ __forceinline__ void stream_tile(const InstDesc& d, int tile, int grp
                         if (m <= d.NOm)
                             gsum = fma(vr[4 + m], fma(l1, cfl[(3 + kMaxNOm + m) * kLanes], cfl[(2 + m) * kLanes]),
                                        gsum);
-                    y += dt * (cA - cB * x) * (wx * gsum - sv[2]);
+                    y += dtc * (cAc - cBc * xc) * ((Tc)(wx * gsum) - sv[2]);
                 }
-                double out;
+                Tc out;
                 if (STAGE == 1) out = y;
-                else if (STAGE == 2) out = 0.75 * (double)rn[i] + 0.25 * y;
-                else out = fma(kTwoThirds, y, kThird * (double)rn[i]);
+                else if (STAGE == 2) out = Tc(0.75) * rn[i] + Tc(0.25) * y;
+                else out = fma(Tc(kTwoThirds), y, Tc(kThird) * rn[i]);
                 if (out_lane) {
                     const Tf o = (Tf)out;
-                    if (!isfinite((double)o)) bad |= 2u;
+                    if (!isfinite(o)) bad |= 2u;
                     fout[(size_t)v * pitch + c] = o;
                 }
             }
@@ -359,6 +363,10 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
         cB = cfl[kLanes];
     }
 
+    // stencil arithmetic in the storage type (per-cell coefficients and the
+    // moment sums stay binary64)
+    using Tc = Tf;
+    const Tc dtc = (Tc)dt, dzic = (Tc)dzi, cAc = (Tc)cA, cBc = (Tc)cB;
     unsigned bad = 0;
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
     // Rounds of W NV velocities, angular-node blocks outer and radial nodes
@@ -426,15 +434,16 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
                     const __attribute__((address_space(4))) double* vr =
                         (const __attribute__((address_space(4))) double*)d.tab.vrec + (size_t)v * kVrec;
                     const double x = vr[0];
+                    const Tc xc = (Tc)x;
                     const Tf* wb = win + (i - i0) * WN;
-                    double sv[6];
+                    Tc sv[6];
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) sv[q] = (double)wb[lane + q];
-                    double F = 0.0;
-                    if (x > 0.0) F = x * weno5(sv[0], sv[1], sv[2], sv[3], sv[4]);
-                    else if (x < 0.0) F = x * weno5(sv[5], sv[4], sv[3], sv[2], sv[1]);
-                    const double Fm = shift_up(F);
-                    double y = (double)(Tf)(sv[2] + dt * (-(F - Fm) * dzi));
+                    for (int q = 0; q < 6; ++q) sv[q] = wb[lane + q];
+                    Tc F = 0;
+                    if (x > 0.0) F = xc * weno5(sv[0], sv[1], sv[2], sv[3], sv[4]);
+                    else if (x < 0.0) F = xc * weno5(sv[5], sv[4], sv[3], sv[2], sv[1]);
+                    const Tc Fm = shift_up(F);
+                    Tc y = sv[2] + dtc * (-(F - Fm) * dzic);
                     if (collide) {
                         const double l1 = vr[2], wx = vr[3];
                         if (p.k == 0) {   // first radial node of this J: its sums over m
@@ -448,15 +457,18 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
                             gJ[i] = g;
                             hJ[i] = hs;
                         }
-                        y += dt * (cA - cB * x) * (wx * fma(l1, hJ[i], gJ[i]) - sv[2]);
+                        // f^eq in binary64 (its Legendre terms grow like gamma^4 at high
+                        // |beta| and partly cancel), rounded once to the stencil type
+                        const Tc fe = (Tc)(wx * fma(l1, hJ[i], gJ[i]));
+                        y += dtc * (cAc - cBc * xc) * (fe - sv[2]);
                     }
-                    double out;
+                    Tc out;
                     if (STAGE == 1) out = y;
-                    else if (STAGE == 2) out = 0.75 * (double)rn[i] + 0.25 * y;
-                    else out = fma(kTwoThirds, y, kThird * (double)rn[i]);
+                    else if (STAGE == 2) out = Tc(0.75) * rn[i] + Tc(0.25) * y;
+                    else out = fma(Tc(kTwoThirds), y, Tc(kThird) * rn[i]);
                     if (out_lane) {
                         const Tf o = (Tf)out;
-                        if (!isfinite((double)o)) bad |= 2u;
+                        if (!isfinite(o)) bad |= 2u;
                         fout[(size_t)v * pitch + c] = o;
                         // moments of the stored output (the next stage's field)
                         const double fo = (double)o, pw = vr[1] * fo;

@@ -47,6 +47,11 @@ __device__ __forceinline__ double shift_up(double x) {
     return __hiloint2double(shi, slo);
 }
 
+__device__ __forceinline__ float shift_up(float x) {
+    const int b = __float_as_int(x);
+    return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x138, 0xf, 0xf, false));
+}
+
 
 // Orders LDS accesses of one wave: LDS executes a wave's instructions in
 // issue order, so keeping the compiler from moving them is enough.

@@ -42,8 +42,8 @@ class PairedEnsemble:
         self.dt = 0.5 / nz
         self.batches = {}
         for Q in (q_lo, q_hi):
-            probs = [rsl.make_problem(nz=nz, dtype=dtype, bc="outflow", tau_r=tau, nL=1.0, TL=1.0, nR=nR, TR=TR,
-                                      kappa=1e9) for (TR, nR, tau) in states]
+            probs = [rsl.make_problem(nz=nz, dtype=dtype, bc="outflow", tau_r=tau, nL=1.0, TL=1.0, nR=nR, TR=TR)
+                     for (TR, nR, tau) in states]
             B = rsl.Batch([self.quads[Q]] * len(states), probs, [self.dt] * len(states))
             B.init()
             self.batches[Q] = B
@@ -176,6 +176,8 @@ def _he_init(seed):
 def evaluate(corr, n_inst, nz, t_end, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=128, dtype="f32", tune=True):
     """Errors of T_lo and of the corrected T_lo against T_hi, and wall times of
     (low-order solve + features + network + correction) vs the high-order solve.
+    When the guard rejects the features, the corrected path's answer is the
+    high-order solve, and its wall time includes that solve.
     With `tune`, both batches first pick their stage-kernel shapes with the
     autotuner (which restores the state it times on), so that neither solve
     runs on untuned defaults."""
@@ -203,6 +205,8 @@ def evaluate(corr, n_inst, nz, t_end, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=
     Tlo = m_lo[:, 2:5]
     def rel(a):
         return float(torch.linalg.norm(a - Thi) / torch.linalg.norm(Thi))
+    if Tc is None:
+        t_learned += t_hi              # the fallback is the plain high-order solve
     out = {"err_lo": rel(Tlo), "t_learned_s": t_learned, "t_high_order_s": t_hi,
            "fallback": Tc is None, "cells": int(Thi.shape[0])}
     if Tc is None:

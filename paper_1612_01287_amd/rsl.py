@@ -64,12 +64,13 @@ _sig("rsl_make_quadrature", ctypes.c_int,
 _sig("rsl_free_quadrature", None, [_vp])
 _sig("rsl_quad_table", ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)])
 _sig("rsl_pitch", ctypes.c_int, [ctypes.c_int])
+_sig("rsl_max_dt", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _dp, _dp])
 _sig("rsl_sizes", ctypes.c_int, [_vp, ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t),
                                  ctypes.POINTER(ctypes.c_size_t)])
 _sig("rsl_init", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _vp])
 _sig("rsl_step", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _dp, ctypes.c_double,
                                 ctypes.c_int, _vp])
-_sig("rsl_moments", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _vp, _vp])
+_sig("rsl_moments", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_status", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp])
 _sig("rsl_last_error", ctypes.c_char_p, [])
 
@@ -126,6 +127,13 @@ class Quadrature:
         if h and _lib is not None:
             _lib.rsl_free_quadrature(h)
             self._h = None
+
+
+def max_dt(quad, problem):
+    """(CFL bound, stiffness bound) on dt that rsl_step's guards apply (host only)."""
+    a, b = ctypes.c_double(0), ctypes.c_double(0)
+    check(_lib.rsl_max_dt(quad.handle, ctypes.byref(problem), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def make_problem(kind="sod", nz=400, dtype="f64", bc="outflow", tau_mode="const", gas="ideal",
@@ -185,11 +193,13 @@ class Instance:
     def set_f(self, values):
         self.f().copy_(torch.as_tensor(values, dtype=self.tdtype))
 
-    def moments(self, stream=None):
-        out = torch.empty((self.nz, C["RSL_NMOM"]), dtype=torch.float64, device=self.f_buf.device)
+    def moments(self, stream=None, fields=None):
+        """[nz, fields] per-cell fields (RSL_MOM_ALL by default, or RSL_MOM_RAW5)."""
+        fields = C["RSL_MOM_ALL"] if fields is None else int(fields)
+        out = torch.empty((self.nz, fields), dtype=torch.float64, device=self.f_buf.device)
         f, w = self._ptrs()
         check(_lib.rsl_moments(self.quad.handle, ctypes.byref(self.p), f, w, ctypes.c_void_p(out.data_ptr()),
-                               _stream(stream)))
+                               fields, _stream(stream)))
         return out
 
     def status(self, stream=None):
@@ -209,8 +219,9 @@ _sig("rsl_batch_stage", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_graph_step", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_set_path", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("rsl_batch_groups", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.c_int])
-_sig("rsl_batch_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
+_sig("rsl_batch_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_status", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)])
+_sig("rsl_batch_instance_status", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)])
 _ip = ctypes.POINTER(ctypes.c_int)
 _sig("rsl_stage_variant", ctypes.c_int, [ctypes.c_int, _ip, _ip, _ip, _ip, _ip, _ip])
 _sig("rsl_batch_variant", ctypes.c_int, [_vp, ctypes.c_int, _ip, _ip])
@@ -316,11 +327,12 @@ class Batch:
         flat = self.f_buf[off.value: off.value + q.V * pitch * es].view(self.tdtype)
         return flat.view(q.V, pitch)[:, :nz]
 
-    def moments(self, stream=None):
+    def moments(self, stream=None, fields=None):
+        fields = C["RSL_MOM_ALL"] if fields is None else int(fields)
         rows = sum(p.nz if p.problem == C["RSL_SOD"] else 1 for p in self.problems)
-        out = torch.empty((rows, C["RSL_NMOM"]), dtype=torch.float64, device=self.f_buf.device)
+        out = torch.empty((rows, fields), dtype=torch.float64, device=self.f_buf.device)
         f, w = self._ptrs()
-        check(_lib.rsl_batch_moments(self._h, f, w, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        check(_lib.rsl_batch_moments(self._h, f, w, ctypes.c_void_p(out.data_ptr()), fields, _stream(stream)))
         return out
 
     def status(self, stream=None):
@@ -328,6 +340,13 @@ class Batch:
         bad = ctypes.c_int(-1)
         rc = _lib.rsl_batch_status(self._h, w, _stream(stream), ctypes.byref(bad))
         return rc, bad.value
+
+    def instance_status(self, stream=None):
+        """Status code (0 or RSL_ENONFINITE) of every instance."""
+        _, w = self._ptrs()
+        out = (ctypes.c_int * self.n)()
+        check(_lib.rsl_batch_instance_status(self._h, w, _stream(stream), out))
+        return list(out)
 
     def __del__(self):
         h = getattr(self, "_h", None)

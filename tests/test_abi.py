@@ -97,3 +97,41 @@ def test_stage_variants_cover_every_class(rsl):
         assert any(c >= bound for c in fused)
     assert max(fused) == 384
     assert {v[5] for v in vs} == {0, 1, 2}
+
+
+@pytest.mark.parametrize("nL,TL,nR,TR", [(1.0, 1.0, 0.4, 0.8), (1.0, 1.0, 0.125, 0.5), (1.0, 1.0, 1 / 27, 1 / 3),
+                                         (0.4, 0.8, 1.0, 1.0)])
+def test_stiffness_guard_uses_riemann_plateau(rsl, nL, TL, nR, TR):
+    """The stiffness bound is kappa over the largest AW rate gamma (1 + |beta|)/tau
+    (eq. L_Sod) at the states of the inviscid Riemann solution (Sec. IV B 1),
+    whose plateau velocity the oracle's exact solver gives independently."""
+    from oracle import riemann
+    q = rsl.Quadrature(3, 8, 3, host_only=True)
+    hi_left = nL * TL >= nR * TR
+    st = riemann.riemann_star(nL, nL * TL, nR, nR * TR) if hi_left else riemann.riemann_star(nR, nR * TR, nL, nL * TL)
+    speed = np.sqrt((1 + st["beta_C"]) / (1 - st["beta_C"]))
+    p = rsl.make_problem(nz=400, tau_r=1e-3, nL=nL, TL=TL, nR=nR, TR=TR)
+    cfl, stiff = rsl.max_dt(q, p)
+    assert cfl == pytest.approx(1.0 / 400 / np.max(q.table(rsl.RSL_TAB_XI)), rel=1e-15)
+    assert stiff == pytest.approx(2.0 * 1e-3 / speed, rel=1e-9)
+    # the eta/s law: the plateau states' own relaxation times (eq. Sod:tau)
+    taw0 = 0.3854 * 0.1
+    p = rsl.make_problem(nz=400, tau_mode="etas", tau_aw0=taw0, nL=nL, TL=TL, nR=nR, TR=TR)
+    _, stiff = rsl.max_dt(q, p)
+    tau = lambda n, T: taw0 / T * (1 - 0.25 * np.log(n / T ** 3))
+    PC = st["PC"]
+    nI, nII = (st["nI"], st["nII"]) if hi_left else (st["nII"], st["nI"])
+    rates = [1 / tau(nL, TL), 1 / tau(nR, TR), speed / tau(nI, PC / nI), speed / tau(nII, PC / nII)]
+    assert stiff == pytest.approx(2.0 / max(rates), rel=1e-9)
+
+
+def test_stiffness_guard_limits(rsl):
+    q = rsl.Quadrature(3, 8, 3, host_only=True)
+    cfl, stiff = rsl.max_dt(q, rsl.make_problem(nz=400, tau_mode="inf"))
+    assert stiff == float("inf") and np.isfinite(cfl)
+    cfl, stiff = rsl.max_dt(q, rsl.make_problem(kind="bjorken", tau_mode="const", tau_r=0.3))
+    assert cfl == float("inf") and stiff == pytest.approx(0.6, rel=1e-15)
+    # kappa scales the bound; the near-inviscid tube's dt = 1.25e-3 at tau_r = 1e-3 passes
+    _, s1 = rsl.max_dt(q, rsl.make_problem(nz=400, tau_r=1e-3, kappa=1.0))
+    _, s2 = rsl.max_dt(q, rsl.make_problem(nz=400, tau_r=1e-3))
+    assert s2 == pytest.approx(2 * s1, rel=1e-15) and s2 > 1.25e-3

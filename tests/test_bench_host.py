@@ -48,62 +48,87 @@ def test_kernel_form_labels(bench):
     assert bench.kernel_forms(per_class + [split[-1]]) == "all:s"
 
 
-def test_traffic_record_selected_by_sources_and_forms(bench):
-    """The committed counter record is used only for the kernel sources and
-    launch forms it was taken with."""
+def test_traffic_record_selected_by_sources_and_forms(bench, tmp_path, monkeypatch):
+    """A counter record is used only for the kernel sources and launch forms
+    it was taken with."""
     from paper_1612_01287_amd import rsl
-    rec = {}
-    with open(bench.TRAFFIC_FILE) as fh:
-        for line in fh:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                rec[k.strip()] = v.strip()
     loop, split, _ = _loop_and_split(rsl)
     n = rsl.N_CLASSES
     merged_loop = [split[0]] * 4 + [-1] * (n - 4) + [loop[0]]
     per_class_split = [split[0]] * 4 + [-1] * (n - 4) + [-1]
-    for dt in ("f64", "f32"):
-        got = bench.measured_traffic(dt, merged_loop)
-        if rec.get("kernel_source_hash") == bench.kernel_source_hash() and rec.get("kernel_forms_" + dt) == "all:l":
-            assert got == pytest.approx(float(rec["bytes_per_stage_group_" + dt]))
-        else:
-            assert got is None
-        assert bench.measured_traffic(dt, per_class_split) is None
+    rec = tmp_path / "rec.txt"
+    monkeypatch.setitem(bench.TRAFFIC_FILES, "ensemble", str(rec))
+    assert bench.measured_traffic("ensemble", merged_loop) is None            # no record
+    rec.write_text("# comment\nbytes_per_stage: 1.5e9\nkernel_forms: all:l\nkernel_source_hash: %s\n"
+                   % bench.kernel_source_hash())
+    assert bench.measured_traffic("ensemble", merged_loop) == pytest.approx(1.5e9)
+    assert bench.measured_traffic("ensemble", per_class_split) is None        # other launch forms
+    rec.write_text("bytes_per_stage: 1.5e9\nkernel_forms: all:l\nkernel_source_hash: 0000\n")
+    assert bench.measured_traffic("ensemble", merged_loop) is None            # other kernel sources
+
+
+def test_committed_traffic_records_parse(bench):
+    for path in bench.TRAFFIC_FILES.values():
+        rec = bench.read_record(path)
+        if rec:
+            assert float(rec["bytes_per_stage"]) > 0 and rec["kernel_forms"] and rec["kernel_source_hash"]
 
 
 def test_roofline_arithmetic(bench):
+    cell_vel = 1024 * 3878 * 90
+    for dt, bpc in (("f64", 64), ("f32", 32)):
+        r = bench.roofline(0.3, 600, cell_vel, dt, "ensemble", [-1] * 8, "k")
+        us = 0.3 / 600 * 1e6
+        assert r["avg_launch_us"] == pytest.approx(us, abs=0.01)
+        assert r["bytes_per_launch"] == pytest.approx(bpc / 3.0 * cell_vel)
+        gbs = bpc / 3.0 * cell_vel / (us * 1e-6) / 1e9
+        assert r["achieved"] == pytest.approx(gbs, abs=0.1)
+        assert r["frac"] == pytest.approx(gbs / bench.HBM_PEAK_GBS, abs=1e-4)
+        assert r["peak"] == 8000.0 and r["unit"] == "GB/s" and r["bound"] == "hbm"
+        assert r["traffic"] is None         # no counter record for per-class empty variants
+
+
+def test_timed_replays_use_stream_events(bench):
+    """The headline's time comes from HIP events recorded on the launching
+    stream around exactly the timed graph replays."""
+    recorded = []
+
     class Ev:
         def __init__(self, enable_timing=True):
             pass
 
         def record(self, stream=None):
-            pass
+            recorded.append(stream)
 
         def synchronize(self):
             pass
 
         def elapsed_time(self, other):
-            return 1.0                      # ms per replay of `chunk` steps
+            return 250.0
+
+    class S:
+        def synchronize(self):
+            pass
 
     torch = types.SimpleNamespace(cuda=types.SimpleNamespace(Event=Ev))
     replays = []
 
     class B:
         def graph_step(self, n, stream=None):
-            replays.append(n)
+            replays.append((n, stream))
 
-    cell_vel = bench.NZ * 4 * (24 + 48 + 120 + 300)
-    ups = 3 * cell_vel
-    for dt, bpc in (("f64", 64), ("f32", 32)):
-        replays.clear()
-        r = bench.kernel_roofline(torch, B(), dt, ups, [-1] * 8, 10, None, reps=10)
-        assert replays == [10] * 10
-        ms = 10 * 1.0 / (3 * 10 * 10)      # one RK stage of the whole batch
-        assert r["avg_launch_us"] == pytest.approx(ms * 1e3, abs=0.01)
-        assert r["bytes_per_launch"] == pytest.approx(bpc / 3.0 * cell_vel)
-        gbs = bpc / 3.0 * cell_vel / (ms * 1e-3) / 1e9
-        assert r["achieved"] == pytest.approx(gbs, abs=0.1)
-        assert r["frac"] == pytest.approx(gbs / bench.HBM_PEAK_GBS, abs=1e-4)
-        assert r["peak"] == 8000.0 and r["unit"] == "GB/s" and r["bound"] == "hbm"
-        assert r["traffic"] is None         # no counter record for per-class empty variants
-        assert "%.0f MB" % (3 * bpc / 8 * cell_vel / 1e6) in r["residency"]
+    st = S()
+    done, wall, ev = bench.timed_replays(torch, B(), 20, 50, st)
+    assert done == 60 and replays == [(20, st)] * 3
+    assert recorded == [st, st] and ev == pytest.approx(0.25)
+
+
+def test_ensemble_recipe(bench):
+    p = bench.ensemble_params()
+    assert len(p) == 1024
+    import numpy as np
+    nz = np.array([x[0] for x in p])
+    assert nz.min() >= 256 and nz.max() <= 16384 and 3000 < nz.mean() < 4800
+    assert {x[1] for x in p} == {8, 16, 32, 64}
+    assert all(1 / 3 - 1e-12 <= x[2] <= 1 / 1.1 + 1e-12 for x in p)
+    assert all(1e-4 <= x[3] <= 1 and x[4] == min(0.5 / x[0], 0.5 * x[3]) for x in p)

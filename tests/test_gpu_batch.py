@@ -90,7 +90,7 @@ def _ragged_all_classes(rsl, dtype):
         TR = 1.0 / (1.2 + 0.2 * i)
         probs.append(rsl.make_problem(nz=nz, dtype=dtype, bc="eq" if i % 2 else "outflow", tau_r=0.02 + 0.01 * i,
                                       nL=1.0, TL=1.0, nR=TR ** 3, TR=TR))
-        dts.append(0.4 / nz)
+        dts.append(min(0.4 / nz, 0.5 * (0.02 + 0.01 * i)))
     return quads, probs, dts
 
 
