@@ -492,8 +492,13 @@ def main():
     chunk = max(1, min(100, a.steps))
     with torch.cuda.stream(stream):
         B.init(stream=stream)
-        if a.dev_steps > 0:
-            B.step(a.dev_steps, stream=stream)
+        done_dev = 0
+        while done_dev < a.dev_steps:                 # in pieces, with a progress line each
+            k = min(250, a.dev_steps - done_dev)
+            B.step(k, stream=stream)
+            stream.synchronize()
+            done_dev += k
+            _progress("ensemble: %d of %d development steps" % (done_dev, a.dev_steps))
         if a.variants:
             _apply_variants(rsl, B, a.variants)
         elif not a.no_autotune:

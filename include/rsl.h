@@ -290,6 +290,31 @@ int rsl_batch_status(rsl_batch* b, void* work_dev, void* hip_stream, int* first_
  * a HIP error. */
 int rsl_batch_instance_status(rsl_batch* b, void* work_dev, void* hip_stream, int* status);
 
+/* ------------------------------------------------------------ diagnostics
+ * Reductions of per-cell (or per-sample) field rows on the device, one
+ * workgroup in a fixed summation order; results are written to out_dev on
+ * the stream (asynchronous).  RSL_EINVAL for NULL pointers or bad sizes. */
+
+/* out_dev[c] = dz * sum_{r = row_lo}^{row_hi - 1} m_dev[r * ncols + c] for
+ * c < ncols: the integral over a window of cells (midpoint rule).  With
+ * rsl_moments rows (ncols = RSL_MOM_ALL) columns 11 and 12 give the integrated
+ * heat flux q and shear pressure Pi around a discontinuity (Sec. IV B 3,
+ * eqs. intq, intpi). */
+int rsl_window_integral(const double* m_dev, int nrows, int ncols, double dz, int row_lo, int row_hi, double* out_dev,
+                        void* hip_stream);
+/* Error measure of the Sod convergence test (Sec. IV E, eq. eps_def) between
+ * two RSL_MOM_ALL moment tables of nz cells on the same grid:
+ * eps_j = max_z |d_j - d_j,ref| / (max_z d_j - min_z d_j) for d_j = n, T, gamma;
+ * out_dev = {eps_n, eps_T, eps_gamma, max_j eps_j}. */
+int rsl_sod_eps(const double* m_dev, const double* ref_dev, int nz, double* out_dev, void* hip_stream);
+/* L2 norm of the Bjorken convergence test (Sec. V E, eq. bjork_L2) between two
+ * histories of RSL_MOM_ALL rows sampled at tau = 1 + i dtau, i < nsamples:
+ * L2(A) = sqrt(int dtau' (A - A_ref)^2 / (tau_f - 1)) by the trapezoid rule,
+ * tau_f = 1 + (nsamples - 1) dtau, for A = n, T, P, Pi;
+ * out_dev = {L2(n), L2(T), L2(P), L2(Pi), max_A L2(A)}. */
+int rsl_bjorken_l2(const double* hist_dev, const double* ref_dev, int nsamples, double dtau, double* out_dev,
+                   void* hip_stream);
+
 /* ------------------------------------------------ learned T^{mu nu} correction
  * Not part of the paper: a per-cell network that maps the local moments of a
  * low-order velocity set to the difference between a high-order and the

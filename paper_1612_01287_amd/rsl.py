@@ -355,6 +355,34 @@ class Batch:
             self._h = None
 
 
+_sig("rsl_window_integral", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_int, _vp, _vp])
+_sig("rsl_sod_eps", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp])
+_sig("rsl_bjorken_l2", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp])
+
+
+def window_integral(m, dz, row_lo, row_hi, stream=None):
+    """[ncols] dz * sum of rows row_lo..row_hi-1 of the [nrows, ncols] fp64 table m (device)."""
+    out = torch.empty(m.shape[1], dtype=torch.float64, device=m.device)
+    check(_lib.rsl_window_integral(_p(m), m.shape[0], m.shape[1], float(dz), int(row_lo), int(row_hi), _p(out),
+                                   _stream(stream)))
+    return out
+
+
+def sod_eps(m, ref, stream=None):
+    """[eps_n, eps_T, eps_gamma, eps] of two [nz, RSL_MOM_ALL] moment tables (eq. eps_def)."""
+    out = torch.empty(4, dtype=torch.float64, device=m.device)
+    check(_lib.rsl_sod_eps(_p(m), _p(ref), m.shape[0], _p(out), _stream(stream)))
+    return out
+
+
+def bjorken_l2(hist, ref, dtau, stream=None):
+    """[L2(n), L2(T), L2(P), L2(Pi), max] of two [nsamples, RSL_MOM_ALL] histories (eq. bjork_L2)."""
+    out = torch.empty(5, dtype=torch.float64, device=hist.device)
+    check(_lib.rsl_bjorken_l2(_p(hist), _p(ref), hist.shape[0], float(dtau), _p(out), _stream(stream)))
+    return out
+
+
 _u16p = ctypes.c_void_p
 _sig("rsl_mlp_features", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, ctypes.c_double, _vp, _vp, _vp, _vp])
 _sig("rsl_mlp_to_bf16", ctypes.c_int, [_vp, _vp, _vp])
