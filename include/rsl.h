@@ -352,6 +352,18 @@ size_t rsl_mlp_backward_work(int n);
 int rsl_mlp_backward(const unsigned short* params_bf16, const float* x, const unsigned short* h1,
                      const unsigned short* h2, const float* y, const float* t, int n, float* grad, float* work,
                      void* hip_stream);
+/* rsl_mlp_backward without the caller's workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training
+ * loops, harnesses that forbid hipMalloc).  The partial gradients go to a
+ * scratch array inside the library: 256 x 27395 floats (28 MB) per device,
+ * enough for any n, held until the process ends.  Allocates nothing (the
+ * array's device address is looked up once per device, at the first call).
+ * Results are bitwise those of rsl_mlp_backward.  Calls on one device share
+ * the array: calls that overlap on one GPU (several streams, threads) race,
+ * so serialise them.  RSL_EINVAL for NULL pointers or n <= 0. */
+int rsl_mlp_backward_noalloc(const unsigned short* params_bf16, const float* x, const unsigned short* h1,
+                             const unsigned short* h2, const float* y, const float* t, int n, float* grad,
+                             void* hip_stream);
 /* One Adam step (step >= 1, bias-corrected) on the fp32 parameters; refreshes
  * the bf16 copy. */
 int rsl_mlp_adam(float* params, const float* grad, float* m, float* v, unsigned short* params_bf16, int step, float lr,

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "rsl_math.h"
 
@@ -399,6 +400,49 @@ constexpr size_t kBwdLds = sizeof(WL) + sizeof(BL);
 
 int grid_rows(int n) { return std::max(1, std::min(1024, (n + ROWS - 1) / ROWS)); }
 
+// Scratch of rsl_mlp_backward_noalloc: the partial-gradient rows of the
+// backward kernel's workgroups.  bwd_groups() never exceeds kBwdGroups, so
+// this holds what any sample count needs (28 MB).  Each device holds its own
+// copy until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchFloats = (size_t)kBwdGroups * NPARAM;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per device.
+int scratch_address(float** out) {
+    int dev = -1;
+    int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return set_error(RSL_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if ((rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))) return rc;
+        g_scratch_dev[dev] = (float*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return RSL_OK;
+}
+
+// The backward pass with partial-gradient rows in `work` (bwd_groups(n) x NPARAM floats).
+int launch_backward(const unsigned short* params_bf16, const float* x, const unsigned short* h1,
+                    const unsigned short* h2, const float* y, const float* t, int n, float* grad, float* work,
+                    hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute((const void*)mlp_backward_kernel,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBwdLds);
+    if (attr != hipSuccess) return hip_check(attr, "hipFuncSetAttribute(mlp_backward_kernel)");
+    const int G = bwd_groups(n);
+    hipLaunchKernelGGL(mlp_backward_kernel, dim3(G), dim3(TPB), kBwdLds, s, params_bf16, x, h1, h2, y, t, n, work);
+    int rc = hip_check(hipGetLastError(), "mlp_backward_kernel launch");
+    if (rc) return rc;
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, s, work, G, grad);
+    return hip_check(hipGetLastError(), "grad_reduce_kernel launch");
+}
+
 }  // namespace
 
 }  // namespace rsl
@@ -452,16 +496,20 @@ int rsl_mlp_backward(const unsigned short* params_bf16, const float* x, const un
                      void* hip_stream) {
     if (!params_bf16 || !x || !h1 || !h2 || !y || !t || !grad || !work || n <= 0)
         return set_error(RSL_EINVAL, "bad argument");
-    static const hipError_t attr = hipFuncSetAttribute((const void*)mlp_backward_kernel,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBwdLds);
-    if (attr != hipSuccess) return hip_check(attr, "hipFuncSetAttribute(mlp_backward_kernel)");
-    hipStream_t s = (hipStream_t)hip_stream;
-    const int G = bwd_groups(n);
-    hipLaunchKernelGGL(mlp_backward_kernel, dim3(G), dim3(TPB), kBwdLds, s, params_bf16, x, h1, h2, y, t, n, work);
-    int rc = hip_check(hipGetLastError(), "mlp_backward_kernel launch");
+    return launch_backward(params_bf16, x, h1, h2, y, t, n, grad, work, (hipStream_t)hip_stream);
+}
+
+int rsl_mlp_backward_noalloc(const unsigned short* params_bf16, const float* x, const unsigned short* h1,
+                             const unsigned short* h2, const float* y, const float* t, int n, float* grad,
+                             void* hip_stream) {
+    if (!params_bf16 || !x || !h1 || !h2 || !y || !t || !grad || n <= 0)
+        return set_error(RSL_EINVAL, "bad argument");
+    if ((size_t)bwd_groups(n) * NPARAM > kScratchFloats)
+        return set_error(RSL_EINVAL, "partial gradients exceed the library's scratch");
+    float* work = nullptr;
+    const int rc = scratch_address(&work);
     if (rc) return rc;
-    hipLaunchKernelGGL(grad_reduce_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, s, work, G, grad);
-    return hip_check(hipGetLastError(), "grad_reduce_kernel launch");
+    return launch_backward(params_bf16, x, h1, h2, y, t, n, grad, work, (hipStream_t)hip_stream);
 }
 
 int rsl_mlp_adam(float* params, const float* grad, float* m, float* v, unsigned short* params_bf16, int step, float lr,
