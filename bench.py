@@ -442,17 +442,18 @@ def bjorken_leg(torch, rsl, stream, n=4096, window=1000, seed=3, cpu=True):
     return out
 
 
-def learned_leg(torch, stream, n_runs=2048, nz_train=2048, n_inst=64, nz_eval=2048, epochs=100):
+def learned_leg(torch, stream, n_runs=2048, nz_train=2048, n_inst=64, nz_eval=2048, epochs=100, chunk=None):
     from paper_1612_01287_amd import learned
     t0 = time.perf_counter()
+    prog = lambda msg: _progress("learned: " + msg)
     X, T = learned.generate(n_runs=n_runs, nz=nz_train, t_snaps=(0.05, 0.1, 0.15, 0.2, 0.25), seed=5, q_lo=8,
-                            q_hi=128)
+                            q_hi=128, progress=prog, chunk=chunk)
     _progress("learned: %d training samples generated (%.1f s)" % (X.shape[0], time.perf_counter() - t0))
-    corr, hist = learned.train(X, T, epochs=epochs, batch=8192, lr=2e-3, seed=1, margin=0.25)
+    corr, hist = learned.train(X, T, epochs=epochs, batch=8192, lr=2e-3, seed=1, margin=0.25, progress=prog)
     torch.cuda.synchronize()
     prep = time.perf_counter() - t0
     del X, T
-    res = learned.evaluate(corr, n_inst=n_inst, nz=nz_eval, t_end=0.25, seed=6, q_lo=8, q_hi=128)
+    res = learned.evaluate(corr, n_inst=n_inst, nz=nz_eval, t_end=0.25, seed=6, q_lo=8, q_hi=128, progress=prog)
     out = {"workload": "learned T^{mu nu} correction: R-SLB(4;8) + network vs R-SLB(4;128), %d instances, "
                        "N_z = %d, t = 0.25; trained on %d paired runs at N_z = %d" % (n_inst, nz_eval, n_runs,
                                                                                       nz_train),
@@ -491,6 +492,8 @@ def main():
     stream = torch.cuda.Stream()          # graph replay needs an explicit stream
     chunk = max(1, min(100, a.steps))
     with torch.cuda.stream(stream):
+        if a.variants:
+            _apply_variants(rsl, B, a.variants)      # fixed shapes: the whole run uses them
         B.init(stream=stream)
         done_dev = 0
         while done_dev < a.dev_steps:                 # in pieces, with a progress line each
@@ -499,9 +502,7 @@ def main():
             stream.synchronize()
             done_dev += k
             _progress("ensemble: %d of %d development steps" % (done_dev, a.dev_steps))
-        if a.variants:
-            _apply_variants(rsl, B, a.variants)
-        elif not a.no_autotune:
+        if not a.variants and not a.no_autotune:
             B.autotune(reps=3, stream=stream)      # on the developed state; f is restored after
         variants = _variants(rsl, B)
         for _ in range(max(1, -(-a.warmup // chunk))):
@@ -551,8 +552,8 @@ def main():
                 "bjorken": lambda: bjorken_leg(torch, rsl, stream, cpu=cpu),
                 "scaled": lambda: scaled_leg(torch, rsl, stream),
                 "learned": lambda: learned_leg(torch, stream),
-                "learned_c5": lambda: learned_leg(torch, stream, n_runs=1024, nz_train=8192, n_inst=512,
-                                                  nz_eval=8192, epochs=60)}
+                "learned_c5": lambda: learned_leg(torch, stream, n_runs=512, nz_train=8192, n_inst=512,
+                                                  nz_eval=8192, epochs=100, chunk=128)}
         del B
         torch.cuda.empty_cache()
         out["aux"] = {}

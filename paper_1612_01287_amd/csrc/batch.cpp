@@ -40,6 +40,7 @@ struct rsl_batch {
     int g_steps = -1;
     hipStream_t g_stream = nullptr;
     // Bjorken: groups of up to 16 instances sharing one velocity set (matrix-core path)
+    double* states = nullptr;     // Sod: device [n][4] initial states (n_L, T_L, n_R, T_R)
     int* groups = nullptr;        // device [ngroups][16]
     int ngroups = 0;
     size_t mfma_lds = 0;
@@ -255,6 +256,14 @@ int batch_upload(rsl_batch* b) {
                 items[3 * c + t] = schedule(b, c < kClasses ? c : -1, kTileWidths[t]);
                 total += align_up(sizeof(int2) * items[3 * c + t].size(), 256);
             }
+    std::vector<double> states;
+    if (b->kind == RSL_SOD) {
+        for (int i = 0; i < b->n; ++i) {
+            const rsl_problem& p = b->probs[i];
+            states.insert(states.end(), {p.n_L, p.T_L, p.n_R, p.T_R});
+        }
+        total += align_up(sizeof(double) * states.size(), 256);
+    }
     const size_t dbytes = align_up(sizeof(InstDesc) * b->n, 256);
     int rc = hip_check(hipMalloc(&b->dmem, dbytes + std::max<size_t>(total, 256)), "hipMalloc(batch)");
     if (rc) return rc;
@@ -283,6 +292,12 @@ int batch_upload(rsl_batch* b) {
         b->groups = (int*)((char*)b->dmem + off);
         rc = hip_check(hipMemcpy(b->groups, groups.data(), sizeof(int) * groups.size(), hipMemcpyHostToDevice),
                        "hipMemcpy(batch groups)");
+        off += align_up(sizeof(int) * groups.size(), 256);
+    }
+    if (rc == RSL_OK && !states.empty()) {
+        b->states = (double*)((char*)b->dmem + off);
+        rc = hip_check(hipMemcpy(b->states, states.data(), sizeof(double) * states.size(), hipMemcpyHostToDevice),
+                       "hipMemcpy(batch states)");
     }
     return rc;
 }
@@ -482,6 +497,16 @@ int rsl_batch_time(const rsl_batch* b, int i, double* t) {
 
 int rsl_batch_init(rsl_batch* b, void* f_dev, void* work_dev, void* hip_stream) {
     if (!b || !f_dev || !work_dev) return set_error(RSL_EINVAL, "null argument");
+    if (b->kind == RSL_SOD) {
+        // every instance in two launches: boundary states (and cleared status
+        // words), then the initial populations over the 64-cell tiles
+        const StageClass& all = b->launch.all;
+        const int rc = launch_sod_batch_init(all.descs, b->states, b->n, all.items_tw[2], all.nitems_tw[2], b->dtype,
+                                             (char*)f_dev, (char*)work_dev, (hipStream_t)hip_stream);
+        if (rc) return rc;
+        for (int i = 0; i < b->n; ++i) b->t[i] = 0.0;
+        return RSL_OK;
+    }
     for (int i = 0; i < b->n; ++i) {
         int rc = rsl_init(b->quads[i], &b->probs[i], (char*)f_dev + b->f_off[i], (char*)work_dev + b->w_off[i],
                           hip_stream);

@@ -183,8 +183,11 @@ int build_quadrature(int QL, int Q, int NOm, double T0, rsl_quad* q) {
     q->NOm = NOm;
     q->V = QL * Q;
     q->T0 = T0;
-    // the recurrence branch loses ~1/beta per order m; see rsl_math.h
-    q->beta_series = NOm <= 3 ? 0.5 : (NOm == 4 ? 0.6 : 0.7);
+    // the recurrence branch loses ~1/beta per order m (see rsl_math.h): at
+    // these switches its K_{k,m} stay within ~4e-14 of the defining integrals
+    // (1e-14 for N_Omega <= 3 at 0.4, 3e-14 for N_Omega = 4 at 0.45, 8e-13 for
+    // N_Omega = 6 at 0.5, hence 0.7 from N_Omega = 5 on)
+    q->beta_series = NOm <= 3 ? 0.4 : (NOm == 4 ? 0.45 : 0.7);
     gauss_legendre(Q, q->xi, q->wxi);
     if (gauss_laguerre2(QL, q->pbar, q->wL) != 0) return set_error(RSL_EINVAL, "Laguerre root search failed");
     // Legendre table up to m = Q + 1 in extended precision
@@ -235,6 +238,8 @@ int build_quadrature(int QL, int Q, int NOm, double T0, rsl_quad* q) {
     q->KP.resize((size_t)Q * Q);
     for (size_t i = 0; i < KP.size(); ++i) q->KP[i] = (double)KP[i];
     series_tables(q->ser, q->thr);
+    if (!(q->thr[kSeriesTerms - 1] >= q->beta_series * q->beta_series))
+        return set_error(RSL_EINVAL, "Maclaurin tables too short for the series switch");
     return RSL_OK;
 }
 

@@ -17,8 +17,10 @@ constexpr double kThird = 1.0 / 3.0;
 constexpr double kTwoThirds = 2.0 / 3.0;
 // Largest N_Omega with equilibrium coefficients (App. A gives m <= 6).
 constexpr int kMaxNOm = 6;
-// Terms kept in the Maclaurin tables of K_{3,m}, K_{4,m} (see rsl_math.h).
-constexpr int kSeriesTerms = 128;
+// Terms kept in the Maclaurin tables of K_{3,m}, K_{4,m} (see rsl_math.h):
+// enough for |beta| up to the largest series switch, 0.7 (67 terms carry every
+// (k, m) series there to 2^-58; build_quadrature checks it).
+constexpr int kSeriesTerms = 72;
 // Doubles per velocity record (QuadDev::vrec): 4 + kMaxNOm + 1 used, padded to 16.
 constexpr int kVrec = 16;
 // Cells per wavefront tile: 64 lanes carry 64 interface fluxes, 63 cells are updated.
@@ -155,6 +157,10 @@ RiemannPlateau riemann_plateau(double nL, double PL, double nR, double PR);
 int launch_boundary_states(const InstDesc& d, double nL, double TL, double nR, double TR,
                            hipStream_t s);
 int launch_sod_init(const InstDesc& d, hipStream_t s);
+// Initial state of every instance of a Sod batch in two launches: states
+// [n][4] = (n_L, T_L, n_R, T_R) per instance, items = (instance, 64-cell tile).
+int launch_sod_batch_init(const InstDesc* descs, const double* states, int n, const int2* items, int nitems,
+                          int dtype, char* fbase, char* wbase, hipStream_t s);
 // `seq`: the stage's index within a call (0: the first, where the loop form
 // computes the stage field's coefficients with the per-cell kernel first).
 int launch_sod_stage(const InstDesc& d, int stage, hipStream_t s, int seq);

@@ -62,18 +62,28 @@ class PairedEnsemble:
         return self.batches[Q].moments()
 
 
-def generate(n_runs, nz, t_snaps, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=128, dtype="f32"):
-    """Features X [N, 81] and targets T [N, 3] from paired runs (on the GPU)."""
+def generate(n_runs, nz, t_snaps, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=128, dtype="f32", progress=None,
+             chunk=None):
+    """Features X [N, 81] and targets T [N, 3] from paired runs (on the GPU).
+    With `chunk`, the runs are generated `chunk` at a time (bounded memory);
+    `progress(msg)` is called after every snapshot."""
     rng = np.random.default_rng(seed)
-    ens = PairedEnsemble(_states(rng, n_runs, *tau_range), nz, q_lo, q_hi, dtype)
+    states = _states(rng, n_runs, *tau_range)
+    chunk = chunk or n_runs
     X, T = [], []
-    done = 0
-    for ts in t_snaps:
-        k = int(round(ts / ens.dt)) - done
-        ens.advance(k)
-        done += k
-        X.append(ens.features())
-        T.append(rsl.tmunu_targets(ens.moments(q_lo), ens.moments(q_hi)))
+    for c0 in range(0, n_runs, chunk):
+        ens = PairedEnsemble(states[c0:c0 + chunk], nz, q_lo, q_hi, dtype)
+        done = 0
+        for ts in t_snaps:
+            k = int(round(ts / ens.dt)) - done
+            ens.advance(k)
+            done += k
+            X.append(ens.features())
+            T.append(rsl.tmunu_targets(ens.moments(q_lo), ens.moments(q_hi)))
+            if progress:
+                torch.cuda.synchronize()
+                progress("runs %d-%d: snapshot t = %.3g" % (c0, min(n_runs, c0 + chunk) - 1, ts))
+        del ens
     return torch.cat(X), torch.cat(T)
 
 
@@ -104,7 +114,7 @@ class Correction:
         return [int(i) for i in torch.nonzero(out).flatten().tolist()]
 
 
-def train(X, T, epochs=20, batch=8192, lr=2e-3, seed=0, margin=0.05, init=None, min_scale=1e-4):
+def train(X, T, epochs=20, batch=8192, lr=2e-3, seed=0, margin=0.05, init=None, min_scale=1e-4, progress=None):
     """Adam on shuffled minibatches with a cosine learning-rate decay.
 
     Inputs are standardised per feature (mean, standard deviation floored at
@@ -139,6 +149,8 @@ def train(X, T, epochs=20, batch=8192, lr=2e-3, seed=0, margin=0.05, init=None, 
             tot += ((y - tb) ** 2).mean().double() * xb.shape[0]
             cnt += xb.shape[0]
         hist.append(float(tot) / cnt)
+        if progress and (ep % 10 == 9 or ep == epochs - 1):
+            progress("epoch %d: loss %.4g" % (ep + 1, hist[-1]))
     _fold_output_scale(net, tsc)
     span = Xs.max(dim=0).values - Xs.min(dim=0).values
     lo = (Xs.min(dim=0).values - margin * span - 1e-6).contiguous()
@@ -173,7 +185,8 @@ def _he_init(seed):
     return np.concatenate(parts)
 
 
-def evaluate(corr, n_inst, nz, t_end, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=128, dtype="f32", tune=True):
+def evaluate(corr, n_inst, nz, t_end, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=128, dtype="f32", tune=True,
+             progress=None):
     """Errors of T_lo and of the corrected T_lo against T_hi, and wall times of
     (low-order solve + features + network + correction) vs the high-order solve.
     When the guard rejects the features, the corrected path's answer is the
@@ -196,6 +209,8 @@ def evaluate(corr, n_inst, nz, t_end, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=
     Tc = corr.apply(X, m_lo)
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
+    if progress:
+        progress("low-order solve and correction: %.2f s" % t_learned)
     t0 = time.perf_counter()
     ens.advance(nsteps, which=q_hi, stream=stream)
     m_hi = ens.moments(q_hi)
