@@ -67,10 +67,11 @@ __device__ __forceinline__ void cell_chain(const InstDesc& d, const double (&M)[
     out[0] = cs.gamma * it;
     out[stride] = cs.gamma * cs.beta * it;
 #pragma unroll
-    for (int m = 0; m <= kMaxNOm; ++m) {
-        out[(2 + m) * stride] = c0[m];
-        out[(3 + kMaxNOm + m) * stride] = c1[m];
-    }
+    for (int m = 0; m <= kMaxNOm; ++m)      // the rows in use (the readers skip the rest)
+        if (m <= d.NOm) {
+            out[(2 + m) * stride] = c0[m];
+            out[(3 + kMaxNOm + m) * stride] = c1[m];
+        }
 }
 
 // WC waves split the velocity sum of 64 cells (one lane per cell).
@@ -526,8 +527,8 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
     cell_chain(d, M, out_lane, d.cell + c, pitch, sh.ser, sh.thr);
 }
 
-template <typename Tf, int STAGE, int W, int NV, int K, int OCC>
-__global__ void __launch_bounds__(W * 64, OCC > 0 ? OCC : 1) loop_batch_kernel(const InstDesc* __restrict__ descs,
+template <typename Tf, int STAGE, int W, int NV, int K>
+__global__ void __launch_bounds__(W * 64) loop_batch_kernel(const InstDesc* __restrict__ descs,
                                                            const int2* __restrict__ items, char* fbase,
                                                            char* wbase) {
     __shared__ LoopLds<Tf, W> sh;
@@ -541,13 +542,13 @@ __global__ void __launch_bounds__(W * 64, OCC > 0 ? OCC : 1) loop_batch_kernel(c
 // The loop kernel, preceded by the per-cell kernel (WC waves, 64-cell tiles)
 // at the first stage of a call (seq == 0).  Batches only: one instance has too
 // few tiles for one workgroup per tile to fill the GPU.
-template <typename Tf, int STAGE, int W, int NV, int WC, int K, int OCC>
+template <typename Tf, int STAGE, int W, int NV, int WC, int K>
 int launch_loop_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStream_t s, int seq) {
     if (d) return set_error(RSL_EUNSUPPORTED, "the loop form of the Sod stage runs in batches only");
     if (seq == 0)
         hipLaunchKernelGGL((cell_batch_kernel<Tf, STAGE, WC>), dim3(cl->nitems_tw[2]), dim3(WC * 64), 0, s, cl->descs,
                            cl->items_tw[2], fb, wb);
-    hipLaunchKernelGGL((loop_batch_kernel<Tf, STAGE, W, NV, K, OCC>), dim3(cl->nitems), dim3(W * 64), 0, s, cl->descs,
+    hipLaunchKernelGGL((loop_batch_kernel<Tf, STAGE, W, NV, K>), dim3(cl->nitems), dim3(W * 64), 0, s, cl->descs,
                        cl->items, fb, wb);
     return hip_check(hipGetLastError(), "sod loop-form stage launch");
 }
@@ -586,8 +587,8 @@ int launch_cls(int var, const InstDesc* d, const StageClass* cl, char* fb, char*
     case id: return launch_split_t<Tf, STAGE, W, NV, WC>(d, cl, fb, wb, s);
         RSL_SPLIT_VARIANTS(RSL_CASE)
 #undef RSL_CASE
-#define RSL_CASE(id, W, NV, WC, K, OCC) \
-    case id: return launch_loop_t<Tf, STAGE, W, NV, WC, K, OCC>(d, cl, fb, wb, s, seq);
+#define RSL_CASE(id, W, NV, WC, K) \
+    case id: return launch_loop_t<Tf, STAGE, W, NV, WC, K>(d, cl, fb, wb, s, seq);
         RSL_LOOP_VARIANTS(RSL_CASE)
 #undef RSL_CASE
         default: return set_error(RSL_EINVAL, "unknown stage kernel variant");

@@ -393,11 +393,9 @@ int launch_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStr
     X(16, 8, 2, 16) X(17, 8, 1, 16) X(18, 2, 4, 16)
 // Variants of the loop form (sod_split.h): waves W walking the velocity set
 // NV velocities at a time with K rounds of loads in flight, cell-kernel waves
-// WC for the first stage of a call, and OCC > 0 to bound the registers so that
-// OCC waves fit per SIMD (the closing per-cell chain then spills a little).
+// WC for the first stage of a call.
 #define RSL_LOOP_VARIANTS(X) \
-    X(19, 8, 2, 8, 2, 0) X(20, 8, 1, 8, 4, 0) X(21, 8, 1, 8, 2, 0) X(22, 8, 1, 8, 3, 0) X(23, 8, 1, 8, 2, 8) \
-    X(24, 8, 1, 8, 3, 8)
+    X(19, 8, 2, 8, 2) X(20, 8, 1, 8, 4) X(21, 8, 1, 8, 2) X(22, 8, 1, 8, 3)
 
 }  // namespace
 

@@ -18,7 +18,7 @@ bool stage_variant_shape(int var, int* W, int* NV, int* TW, int* form, int* WC) 
     case id: *W = w; *NV = nv; *TW = kLanes; *form = kFormSplit; *WC = wc; return true;
         RSL_SPLIT_VARIANTS(RSL_SHAPE)
 #undef RSL_SHAPE
-#define RSL_SHAPE(id, w, nv, wc, k, occ) \
+#define RSL_SHAPE(id, w, nv, wc, k) \
     case id: *W = w; *NV = nv; *TW = kLanes; *form = kFormLoop; *WC = wc; return true;
         RSL_LOOP_VARIANTS(RSL_SHAPE)
 #undef RSL_SHAPE
