@@ -6,8 +6,10 @@ code with the HIP library in ``paper_1612_01287_amd/`` and never imports it.
 
 Layout: ``rslo.c`` holds the solver arithmetic (plain C, FP64, no FMA
 contraction); ``quadrature.py`` the velocity-set tables; the analytic and
-semi-analytic references the paper compares against live in ``riemann.py``,
-``ballistic.py``, ``bjorken_ref.py``.  This module wraps ``rslo.c`` with ctypes.
+semi-analytic references the paper compares against live in ``riemann.py`` and
+``bjorken_ref.py``; the field diagnostics (window integrals, the Sod error
+measure, the Bjorken L2 norm) in ``diagnostics.py``; the reference network of
+the learned correction in ``mlp.py``.  This module wraps ``rslo.c`` with ctypes.
 
 Parity status per function (pins in tests/test_oracle_*.py):
   quadrature, K^L, K^P ........ pinned (exactness, Table I, calculus identities)
@@ -21,6 +23,11 @@ Parity status per function (pins in tests/test_oracle_*.py):
                                 3rd order in dt, 5th order in dz for free streaming)
   Bjorken step ................ pinned (tau n = 1, energy identity, free streaming,
                                 ideal-fluid limit, 3rd-order RK convergence)
+  diagnostics ................. pinned (window integral, eps and L2 on profiles with
+                                closed-form values; the analytic q and Pi integrals
+                                against a near-inviscid kinetic solve)
+  reference network ........... pinned (finite-difference gradients, Adam on a
+                                quadratic, feature definitions)
 """
 import ctypes
 import os
