@@ -215,10 +215,13 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
 // weights are formed as ratios, w_q ~ delta_q (sigma_min / sigma_q)^2 in
 // [0, delta_q], which neither overflow nor underflow whatever the scale of
 // the populations (delta_q / sigma_q^2 itself overflows binary32 for smooth
-// data); equal indicators give exactly the ideal weights.  Stencils with a
-// vanishing or denormal-range indicator are rare outside flat regions: all
-// equal (flat data) takes the ideal weights here, the other limiting cases
-// go through the binary64 flux above.
+// data); equal indicators give exactly the ideal weights.  The limiting
+// cases are decided on the binary32 indicators: all equal (flat data) takes
+// the ideal weights, exact zeros among unequal indicators (the edges of flat
+// regions) weight the vanishing stencils by their ideal weights (two zero:
+// they share; one zero: it alone).  Only a smallest indicator that is not
+// zero but below 1e-30 (where the squared ratio would lose digits in the
+// denormal range) goes through the binary64 flux above.
 __device__ __forceinline__ float weno5(float a, float b, float c, float d, float e) {
     const float q1 = (2.0f * a - 7.0f * b + 11.0f * c) * (1.0f / 6.0f);
     const float q2 = (-b + 5.0f * c + 2.0f * d) * (1.0f / 6.0f);
@@ -238,6 +241,10 @@ __device__ __forceinline__ float weno5(float a, float b, float c, float d, float
         return (v1 * q1 + v2 * q2 + v3 * q3) * __builtin_amdgcn_rcpf(v1 + v2 + v3);
     }
     if (s1 == s2 && s2 == s3) return 0.1f * q1 + 0.6f * q2 + 0.3f * q3;   // case (i), incl. all zero
+    if (sm == 0.0f) {                                                        // cases (ii), (iii)
+        const float v1 = s1 == 0.0f ? 0.1f : 0.0f, v2 = s2 == 0.0f ? 0.6f : 0.0f, v3 = s3 == 0.0f ? 0.3f : 0.0f;
+        return (v1 * q1 + v2 * q2 + v3 * q3) * __builtin_amdgcn_rcpf(v1 + v2 + v3);
+    }
     return (float)weno5((double)a, (double)b, (double)c, (double)d, (double)e);
 }
 
