@@ -251,8 +251,10 @@ int rsl_make_quadrature(int Q_L, int Q_xi, int N_L, int N_Omega, double T0, int 
             for (int j = 0; j < Q; ++j)
                 for (int k = 0; k < QL; ++k) vpd[o++] = (double)(k * Q + j);
         }
-        // one record of kVrec doubles per velocity: xi_j, p_k, L_1(pbar_k),
-        // w_j w_k, P_0..P_kMaxNOm(xi_j) (read with one scalar-load burst)
+        // one record of kVrec doubles per velocity (read with scalar loads):
+        // xi_j, p_k, L_1(pbar_k), w_j w_k, P_0..P_kMaxNOm(xi_j), xi_j^2,
+        // xi_j / 6, then binary32 xi_j and xi_j / 6, binary32 p_k and the sign
+        // of xi_j as an int (the layout of kVrec* in rsl_impl.h)
         std::vector<double> vrec((size_t)V * kVrec, 0.0);
         for (int v = 0; v < V; ++v) {
             double* r = vrec.data() + (size_t)v * kVrec;
@@ -261,6 +263,12 @@ int rsl_make_quadrature(int Q_L, int Q_xi, int N_L, int N_Omega, double T0, int 
             r[2] = l1v[v];
             r[3] = wxw[v];
             for (int m = 0; m <= q->NOm; ++m) r[4 + m] = Pv[(size_t)m * V + v];
+            r[kVrecXi2] = xv[v] * xv[v];
+            r[kVrecXi6] = xv[v] / 6.0;
+            const float f32[4] = {(float)xv[v], (float)(xv[v] / 6.0), (float)pv[v], 0.0f};
+            std::memcpy(&r[kVrecF32], f32, 3 * sizeof(float));
+            const int sgn = xv[v] > 0.0 ? 1 : (xv[v] < 0.0 ? -1 : 0);
+            std::memcpy(reinterpret_cast<char*>(&r[kVrecF32]) + 3 * sizeof(float), &sgn, sizeof(int));
         }
         const std::vector<double>* parts[] = {&q->xi, &wxw, &pk, &L1, &q->Pm, &q->ser, &q->thr, &q->KL, &q->KP,
                                               &xv, &pv, &l1v, &Pv, &KPt, &vrec, &vpd};

@@ -23,6 +23,11 @@ constexpr int kMaxNOm = 6;
 constexpr int kSeriesTerms = 72;
 // Doubles per velocity record (QuadDev::vrec): 4 + kMaxNOm + 1 used, padded to 16.
 constexpr int kVrec = 16;
+// slots of the per-velocity record past P_0..P_kMaxNOm (entries 4..10)
+constexpr int kVrecXi2 = 11;   // xi_j^2
+constexpr int kVrecXi6 = 12;   // xi_j / 6 (WENO5 candidates are formed six times larger)
+constexpr int kVrecF32 = 13;   // 16 bytes: binary32 xi_j, xi_j / 6, p_k, then int sign(xi_j)
+static_assert(4 + kMaxNOm < kVrecXi2 && kVrecF32 + 2 <= kVrec, "velocity record layout");
 // Cells per wavefront tile: 64 lanes carry 64 interface fluxes, 63 cells are updated.
 constexpr int kLanes = 64;
 constexpr int kTileCells = kLanes - 1;

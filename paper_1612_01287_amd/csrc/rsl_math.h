@@ -170,20 +170,27 @@ __device__ __forceinline__ void feq_coef(double n, double T, double beta, double
 // w_q ~ delta_q / sigma_q^2 with delta = (1/10, 6/10, 3/10) and no epsilon
 // regulariser; the paper's limiting cases for vanishing indicators are
 // honoured: all equal -> ideal weights; two zero -> the two share by their
-// ideal weights; one zero -> that stencil alone.  The common case uses the
-// common denominator sigma_1^2 sigma_2^2 sigma_3^2 (equal indicators then give
-// the ideal weights to rounding) and a reciprocal refined by two Newton steps;
-// exact zeros and products outside [1e-280, 1e280] take the explicit branch.
-__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
-    const double q1 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
-    const double q2 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
-    const double q3 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
+// ideal weights; one zero -> that stencil alone.
+//
+// weno5_6 returns six times the interface value: the three candidates are
+// taken without their common factor 1/6 (callers fold it into the velocity
+// xi_j / 6), and the indicators are taken four times larger,
+// (13/3) r^2 + t^2, which leaves the normalised weights and the tests for
+// equal or vanishing indicators unchanged (scaling by 4 is exact).  The
+// common case uses the common denominator sigma_1^2 sigma_2^2 sigma_3^2
+// (equal indicators then give the ideal weights to rounding) and a reciprocal
+// refined by two Newton steps; exact zeros and products outside
+// [1e-280, 1e280] take the explicit branch.
+__device__ __forceinline__ double weno5_6(double a, double b, double c, double d, double e) {
+    const double q1 = 2.0 * a - 7.0 * b + 11.0 * c;
+    const double q2 = -b + 5.0 * c + 2.0 * d;
+    const double q3 = 2.0 * c + 5.0 * d - e;
     const double r1 = a - 2.0 * b + c, t1 = a - 4.0 * b + 3.0 * c;
     const double r2 = b - 2.0 * c + d, t2 = b - d;
     const double r3 = c - 2.0 * d + e, t3 = 3.0 * c - 4.0 * d + e;
-    const double s1 = (13.0 / 12.0) * r1 * r1 + 0.25 * t1 * t1;
-    const double s2 = (13.0 / 12.0) * r2 * r2 + 0.25 * t2 * t2;
-    const double s3 = (13.0 / 12.0) * r3 * r3 + 0.25 * t3 * t3;
+    const double s1 = (13.0 / 3.0) * r1 * r1 + t1 * t1;
+    const double s2 = (13.0 / 3.0) * r2 * r2 + t2 * t2;
+    const double s3 = (13.0 / 3.0) * r3 * r3 + t3 * t3;
     const double u1 = s1 * s1, u2 = s2 * s2, u3 = s3 * s3;
     const double w1 = 0.1 * u2 * u3, w2 = 0.6 * u1 * u3, w3 = 0.3 * u1 * u2;
     const double den = w1 + w2 + w3;
@@ -211,29 +218,29 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
     return (v1 * q1 + v2 * q2 + v3 * q3) / (v1 + v2 + v3);
 }
 
-// The same flux in binary32, for populations stored in binary32.  The
-// weights are formed as ratios, w_q ~ delta_q (sigma_min / sigma_q)^2 in
-// [0, delta_q], which neither overflow nor underflow whatever the scale of
-// the populations (delta_q / sigma_q^2 itself overflows binary32 for smooth
-// data); equal indicators give exactly the ideal weights.  The limiting
-// cases are decided on the binary32 indicators: all equal (flat data) takes
-// the ideal weights, exact zeros among unequal indicators (the edges of flat
-// regions) weight the vanishing stencils by their ideal weights (two zero:
-// they share; one zero: it alone).  Only a smallest indicator that is not
-// zero but below 1e-30 (where the squared ratio would lose digits in the
-// denormal range) goes through the binary64 flux above.
-__device__ __forceinline__ float weno5(float a, float b, float c, float d, float e) {
-    const float q1 = (2.0f * a - 7.0f * b + 11.0f * c) * (1.0f / 6.0f);
-    const float q2 = (-b + 5.0f * c + 2.0f * d) * (1.0f / 6.0f);
-    const float q3 = (2.0f * c + 5.0f * d - e) * (1.0f / 6.0f);
+// The same in binary32, for populations stored in binary32.  The weights are
+// formed as ratios, w_q ~ delta_q (sigma_min / sigma_q)^2 in [0, delta_q],
+// which neither overflow nor underflow whatever the scale of the populations
+// (delta_q / sigma_q^2 itself overflows binary32 for smooth data); equal
+// indicators give exactly the ideal weights.  The limiting cases are decided
+// on the binary32 indicators: all equal (flat data) takes the ideal weights,
+// exact zeros among unequal indicators (the edges of flat regions) weight the
+// vanishing stencils by their ideal weights (two zero: they share; one zero:
+// it alone).  Only a smallest indicator that is not zero but below 4e-30
+// (where the squared ratio would lose digits in the denormal range) goes
+// through the binary64 form above.
+__device__ __forceinline__ float weno5_6(float a, float b, float c, float d, float e) {
+    const float q1 = 2.0f * a - 7.0f * b + 11.0f * c;
+    const float q2 = -b + 5.0f * c + 2.0f * d;
+    const float q3 = 2.0f * c + 5.0f * d - e;
     const float r1 = a - 2.0f * b + c, t1 = a - 4.0f * b + 3.0f * c;
     const float r2 = b - 2.0f * c + d, t2 = b - d;
     const float r3 = c - 2.0f * d + e, t3 = 3.0f * c - 4.0f * d + e;
-    const float s1 = (13.0f / 12.0f) * r1 * r1 + 0.25f * t1 * t1;
-    const float s2 = (13.0f / 12.0f) * r2 * r2 + 0.25f * t2 * t2;
-    const float s3 = (13.0f / 12.0f) * r3 * r3 + 0.25f * t3 * t3;
+    const float s1 = (13.0f / 3.0f) * r1 * r1 + t1 * t1;
+    const float s2 = (13.0f / 3.0f) * r2 * r2 + t2 * t2;
+    const float s3 = (13.0f / 3.0f) * r3 * r3 + t3 * t3;
     const float sm = fminf(s1, fminf(s2, s3));
-    if (sm > 1e-30f) {
+    if (sm > 4e-30f) {
         const float g1 = sm * __builtin_amdgcn_rcpf(s1);
         const float g2 = sm * __builtin_amdgcn_rcpf(s2);
         const float g3 = sm * __builtin_amdgcn_rcpf(s3);
@@ -245,7 +252,13 @@ __device__ __forceinline__ float weno5(float a, float b, float c, float d, float
         const float v1 = s1 == 0.0f ? 0.1f : 0.0f, v2 = s2 == 0.0f ? 0.6f : 0.0f, v3 = s3 == 0.0f ? 0.3f : 0.0f;
         return (v1 * q1 + v2 * q2 + v3 * q3) * __builtin_amdgcn_rcpf(v1 + v2 + v3);
     }
-    return (float)weno5((double)a, (double)b, (double)c, (double)d, (double)e);
+    return (float)weno5_6((double)a, (double)b, (double)c, (double)d, (double)e);
+}
+
+// The interface value itself.
+template <typename T>
+__device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
+    return weno5_6(a, b, c, d, e) * (T)(1.0 / 6.0);
 }
 
 }  // namespace rsl

@@ -367,9 +367,10 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
     }
 
     // stencil arithmetic in the storage type (per-cell coefficients and the
-    // moment sums stay binary64)
+    // moment sums stay binary64); the relaxation rate is taken with dt folded
+    // in, dt gamma (1 - beta xi) / tau = dtA - dtB xi
     using Tc = Tf;
-    const Tc dtc = (Tc)dt, dzic = (Tc)dzi, cAc = (Tc)cA, cBc = (Tc)cB;
+    const Tc dtdz = (Tc)(dt * dzi), dtA = (Tc)(dt * cA), dtB = (Tc)(dt * cB);
     unsigned bad = 0;
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
     // Rounds of W NV velocities, angular-node blocks outer and radial nodes
@@ -436,17 +437,20 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
                     const int v = p.k * Q + J;
                     const __attribute__((address_space(4))) double* vr =
                         (const __attribute__((address_space(4))) double*)d.tab.vrec + (size_t)v * kVrec;
-                    const double x = vr[0];
-                    const Tc xc = (Tc)x;
+                    const __attribute__((address_space(4))) float* vf =
+                        (const __attribute__((address_space(4))) float*)(vr + kVrecF32);
+                    const int sgn = ((const __attribute__((address_space(4))) int*)vf)[3];
+                    const Tc xc = sizeof(Tc) == 4 ? (Tc)vf[0] : (Tc)vr[0];
+                    const Tc x6 = sizeof(Tc) == 4 ? (Tc)vf[1] : (Tc)vr[kVrecXi6];
                     const Tf* wb = win + (i - i0) * WN;
                     Tc sv[6];
 #pragma unroll
                     for (int q = 0; q < 6; ++q) sv[q] = wb[lane + q];
                     Tc F = 0;
-                    if (x > 0.0) F = xc * weno5(sv[0], sv[1], sv[2], sv[3], sv[4]);
-                    else if (x < 0.0) F = xc * weno5(sv[5], sv[4], sv[3], sv[2], sv[1]);
+                    if (sgn > 0) F = x6 * weno5_6(sv[0], sv[1], sv[2], sv[3], sv[4]);
+                    else if (sgn < 0) F = x6 * weno5_6(sv[5], sv[4], sv[3], sv[2], sv[1]);
                     const Tc Fm = shift_up(F);
-                    Tc y = sv[2] + dtc * (-(F - Fm) * dzic);
+                    Tc y = fma(Fm - F, dtdz, sv[2]);
                     if (collide) {
                         const double l1 = vr[2], wx = vr[3];
                         if (p.k == 0) {   // first radial node of this J: its sums over m
@@ -463,7 +467,7 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
                         // f^eq in binary64 (its Legendre terms grow like gamma^4 at high
                         // |beta| and partly cancel), rounded once to the stencil type
                         const Tc fe = (Tc)(wx * fma(l1, hJ[i], gJ[i]));
-                        y += dtc * (cAc - cBc * xc) * (fe - sv[2]);
+                        y = fma(fma(-dtB, xc, dtA), fe - sv[2], y);
                     }
                     Tc out;
                     if (STAGE == 1) out = y;
@@ -474,12 +478,12 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
                         if (!isfinite(o)) bad |= 2u;
                         fout[(size_t)v * pitch + c] = o;
                         // moments of the stored output (the next stage's field)
-                        const double fo = (double)o, pw = vr[1] * fo;
+                        const double x = vr[0], fo = (double)o, pw = vr[1] * fo;
                         m0 += fo;
-                        m1 += x * fo;
+                        m1 = fma(x, fo, m1);
                         m2 += pw;
-                        m3 += x * pw;
-                        m4 += x * x * pw;
+                        m3 = fma(x, pw, m3);
+                        m4 = fma(vr[kVrecXi2], pw, m4);
                     }
                 }
             }

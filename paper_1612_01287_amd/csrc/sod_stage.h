@@ -395,7 +395,8 @@ int launch_t(const InstDesc* d, const StageClass* cl, char* fb, char* wb, hipStr
 // NV velocities at a time with K rounds of loads in flight, cell-kernel waves
 // WC for the first stage of a call.
 #define RSL_LOOP_VARIANTS(X) \
-    X(19, 8, 2, 8, 2) X(20, 8, 1, 8, 4) X(21, 8, 1, 8, 2) X(22, 8, 1, 8, 3)
+    X(19, 8, 2, 8, 2) X(20, 8, 1, 8, 4) X(21, 8, 1, 8, 2) X(22, 8, 1, 8, 3) X(23, 4, 1, 8, 4) X(24, 4, 1, 8, 5) \
+    X(25, 4, 1, 8, 6) X(26, 4, 1, 8, 3) X(27, 4, 1, 8, 2) X(28, 4, 2, 8, 3)
 
 }  // namespace
 

@@ -52,7 +52,14 @@ def test_window_integral_and_eps_match_oracle(rsl):
         want = dg.window_integral(h0, 1.0 / nz, lo, hi)
         assert np.all(np.abs(got - want) <= 1e-12 * np.maximum(np.abs(want), 1e-300) + 1e-300), (lo, hi)
     got = rsl.sod_eps(M0, M1).cpu().numpy()
-    assert _rel(got, dg.sod_eps(h0, h1)) < 1e-12
+    want = dg.sod_eps(h0, h1)
+    # eps's numerator is a difference of two nearly equal fields (the models
+    # agree to ~1e-5 here), so a last-bit difference in gamma = (1 - beta^2)^-1/2
+    # (the device contracts 1 - beta^2 into one FMA) bounds its error
+    # absolutely: a few ulp of max|d| over max d - min d, ~1e-14
+    fld = dg._fields(h0)
+    scale = max(np.max(np.abs(fld[k])) / (np.max(fld[k]) - np.min(fld[k])) for k in ("n", "T", "gamma"))
+    assert np.all(np.abs(got - want) <= 1e-12 * np.abs(want) + 16 * np.finfo(float).eps * scale), (got, want)
     assert 0 < got[3] < 0.2
 
 
