@@ -67,9 +67,11 @@ __device__ __forceinline__ int series_terms(double x, const double* __restrict__
     return nt;
 }
 
-// The same count for a wave-uniform x (binary search; thr typically a copy in LDS).
-__device__ __forceinline__ int series_terms_uniform(double x, const double* __restrict__ thr) {
-    const double* t = thr;
+// The same count for a wave-uniform x (binary search; thr a copy in LDS, or
+// the table itself through scalar loads when TP is a constant-space pointer).
+template <typename TP>
+__device__ __forceinline__ int series_terms_uniform(double x, TP thr) {
+    TP t = thr;
     int lo = 1, hi = kSeriesTerms;      // first nt in [1, kSeriesTerms) with x <= thr[nt], else kSeriesTerms
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -92,25 +94,49 @@ __device__ __forceinline__ double wave_max_uniform(double x) {
 // when |beta| < beta_s (nt from series_terms for beta^2 or anything larger:
 // extra terms only add values below the last bit).  ser is the term-major
 // coefficient table, in global memory or staged in LDS by the caller.
-__device__ __forceinline__ void kint(double beta, int nom, double beta_s, const double* __restrict__ ser,
-                                     int nt, double* K3, double* K4) {
+// The series sums for a fixed order N, without per-term branches.
+template <int N, typename TP>
+__device__ __forceinline__ void kint_series(double x, TP ser, int nt, double* s3, double* s4) {
+    double p = 1.0;
+#pragma unroll 1
+    for (int i = 0; i < nt; ++i) {
+        TP a = ser + i * 2 * (kMaxNOm + 1);
+#pragma unroll
+        for (int m = 0; m <= N; ++m) {
+            s3[m] = fma(a[m], p, s3[m]);
+            s4[m] = fma(a[kMaxNOm + 1 + m], p, s4[m]);
+        }
+        p *= x;
+    }
+}
+
+template <typename TP>
+__device__ __forceinline__ void kint(double beta, int nom, double beta_s, TP ser, int nt, double* K3, double* K4) {
     const double ab = fabs(beta);
     if (ab < beta_s) {
         const double x = beta * beta;
         double s3[kMaxNOm + 1], s4[kMaxNOm + 1];
 #pragma unroll
         for (int m = 0; m <= kMaxNOm; ++m) s3[m] = s4[m] = 0.0;
-        double p = 1.0;
-        for (int i = 0; i < nt; ++i) {
-            const double* a = ser + i * 2 * (kMaxNOm + 1);
+        switch (nom) {
+            case 3: kint_series<3>(x, ser, nt, s3, s4); break;
+            case 4: kint_series<4>(x, ser, nt, s3, s4); break;
+            case 5: kint_series<5>(x, ser, nt, s3, s4); break;
+            case 6: kint_series<6>(x, ser, nt, s3, s4); break;
+            default: {
+                double p = 1.0;
+                for (int i = 0; i < nt; ++i) {
+                    TP a = ser + i * 2 * (kMaxNOm + 1);
 #pragma unroll
-            for (int m = 0; m <= kMaxNOm; ++m) {
-                if (m <= nom) {
-                    s3[m] = fma(a[m], p, s3[m]);
-                    s4[m] = fma(a[kMaxNOm + 1 + m], p, s4[m]);
+                    for (int m = 0; m <= kMaxNOm; ++m) {
+                        if (m <= nom) {
+                            s3[m] = fma(a[m], p, s3[m]);
+                            s4[m] = fma(a[kMaxNOm + 1 + m], p, s4[m]);
+                        }
+                    }
+                    p *= x;
                 }
             }
-            p *= x;
         }
         double bm = 1.0;
 #pragma unroll
@@ -149,9 +175,9 @@ __device__ __forceinline__ void kint(double beta, int nom, double beta_s, const 
 //   c0[m] = h_m K_{3,m},  c1[m] = h_m (K_{3,m} - (theta/gamma) K_{4,m}),
 //   h_m = n (2m+1) / (8 gamma^3).
 // nt: series terms (see kint).
+template <typename TP>
 __device__ __forceinline__ void feq_coef(double n, double T, double beta, double gamma, double T0,
-                                         int nom, double beta_s, const double* ser, int nt,
-                                         double* c0, double* c1) {
+                                         int nom, double beta_s, TP ser, int nt, double* c0, double* c1) {
     double K3[kMaxNOm + 1], K4[kMaxNOm + 1];
     kint(beta, nom, beta_s, ser, nt, K3, K4);
     const double h0 = n / (8.0 * gamma * gamma * gamma);

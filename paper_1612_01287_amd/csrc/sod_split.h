@@ -45,8 +45,9 @@ struct CellLds {
 // tau (eq. Sod:tau) and the equilibrium coefficients, stored as kCellPar rows
 // (stride apart) at out when live.  Lanes without a cell carry a rest state so
 // that the series term count stays wave-uniform.
+template <typename TP>
 __device__ __forceinline__ void cell_chain(const InstDesc& d, const double (&M)[5], bool live, double* out,
-                                           size_t stride, const double* ser, const double* thr) {
+                                           size_t stride, TP ser, TP thr) {
     CellState cs = landau(M[0], M[1], M[2], M[3], M[4]);
     if (live && !cs.ok) atomicOr(d.status, 1u);
     if (!live || !cs.ok) {
@@ -125,7 +126,7 @@ __device__ __forceinline__ void cell_tile(const InstDesc& d, int tile, CellLds<W
         for (int ww = 1; ww < W; ++ww) sum += red[(ww * 5 + q) * kLanes + lane];
         M[q] = sum;
     }
-    cell_chain(d, M, live, d.cell + c, (size_t)d.pitch, sh.ser, sh.thr);
+    cell_chain(d, M, live, d.cell + c, (size_t)d.pitch, (const double*)sh.ser, (const double*)sh.thr);
 }
 
 // The W waves of a workgroup share one tile: its cells' coefficients are
@@ -316,9 +317,20 @@ struct LoopLds {
         } s;
         double red[W * 5 * kLanes];   // moment sums of the waves (outside the velocity walk)
     } u;
-    double ser[kSerLen];
-    double thr[kSeriesTerms];
 };
+
+// Legendre sums of the equilibrium coefficients at one angular node for
+// N_Omega = N: sum_m P_m(xi_J) c0_m and sum_m P_m(xi_J) c1_m, the record's
+// P_m and the cell's coefficient rows read in one batch.
+template <int N>
+__device__ __forceinline__ void legendre_sums(const __attribute__((address_space(4))) double* vr, const double* cfl,
+                                              double& g, double& hs) {
+#pragma unroll
+    for (int m = 0; m <= N; ++m) {
+        g = fma(vr[4 + m], cfl[(2 + m) * kLanes], g);
+        hs = fma(vr[4 + m], cfl[(3 + kMaxNOm + m) * kLanes], hs);
+    }
+}
 
 template <typename Tf, int STAGE, int W, int NV, int K>
 __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<Tf, W>& sh) {
@@ -349,7 +361,7 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
     // this stage's coefficients of the tile's cells (written by the previous
     // stage's workgroup of this tile; lane 0 reads the tile's first cell
     // instead of its neighbour's, which another workgroup rewrites, and its
-    // result is never stored), and the tables of the closing per-cell chain
+    // result is never stored)
     double cA = 0.0, cB = 0.0;
     const double* cfl = cf + lane;
     if (collide) {
@@ -359,8 +371,6 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
             const int row = r < 2 + d.NOm + 1 ? r : r - (2 + d.NOm + 1) + 3 + kMaxNOm;
             cf[row * kLanes + lane] = d.cell[(size_t)row * pitch + ccf];
         }
-        for (int e = threadIdx.x; e < kSerLen; e += W * kLanes) sh.ser[e] = d.tab.ser[e];
-        for (int e = threadIdx.x; e < kSeriesTerms; e += W * kLanes) sh.thr[e] = d.tab.thr[e];
         __syncthreads();
         cA = cfl[0];
         cB = cfl[kLanes];
@@ -439,9 +449,11 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
                         (const __attribute__((address_space(4))) double*)d.tab.vrec + (size_t)v * kVrec;
                     const __attribute__((address_space(4))) float* vf =
                         (const __attribute__((address_space(4))) float*)(vr + kVrecF32);
+                    // the record's fields, loaded together ahead of the branches
                     const int sgn = ((const __attribute__((address_space(4))) int*)vf)[3];
                     const Tc xc = sizeof(Tc) == 4 ? (Tc)vf[0] : (Tc)vr[0];
                     const Tc x6 = sizeof(Tc) == 4 ? (Tc)vf[1] : (Tc)vr[kVrecXi6];
+                    const double x = vr[0], pk = vr[1], l1 = vr[2], wx = vr[3], x2 = vr[kVrecXi2];
                     const Tf* wb = win + (i - i0) * WN;
                     Tc sv[6];
 #pragma unroll
@@ -452,15 +464,21 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
                     const Tc Fm = shift_up(F);
                     Tc y = fma(Fm - F, dtdz, sv[2]);
                     if (collide) {
-                        const double l1 = vr[2], wx = vr[3];
                         if (p.k == 0) {   // first radial node of this J: its sums over m
                             double g = 0.0, hs = 0.0;
+                            switch (d.NOm) {   // branch-free sums for the usual orders
+                                case 3: legendre_sums<3>(vr, cfl, g, hs); break;
+                                case 4: legendre_sums<4>(vr, cfl, g, hs); break;
+                                case 5: legendre_sums<5>(vr, cfl, g, hs); break;
+                                case 6: legendre_sums<6>(vr, cfl, g, hs); break;
+                                default:
 #pragma unroll
-                            for (int m = 0; m <= kMaxNOm; ++m)
-                                if (m <= d.NOm) {
-                                    g = fma(vr[4 + m], cfl[(2 + m) * kLanes], g);
-                                    hs = fma(vr[4 + m], cfl[(3 + kMaxNOm + m) * kLanes], hs);
-                                }
+                                    for (int m = 0; m <= kMaxNOm; ++m)
+                                        if (m <= d.NOm) {
+                                            g = fma(vr[4 + m], cfl[(2 + m) * kLanes], g);
+                                            hs = fma(vr[4 + m], cfl[(3 + kMaxNOm + m) * kLanes], hs);
+                                        }
+                            }
                             gJ[i] = g;
                             hJ[i] = hs;
                         }
@@ -478,12 +496,12 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
                         if (!isfinite(o)) bad |= 2u;
                         fout[(size_t)v * pitch + c] = o;
                         // moments of the stored output (the next stage's field)
-                        const double x = vr[0], fo = (double)o, pw = vr[1] * fo;
+                        const double fo = (double)o, pw = pk * fo;
                         m0 += fo;
                         m1 = fma(x, fo, m1);
                         m2 += pw;
                         m3 = fma(x, pw, m3);
-                        m4 = fma(vr[kVrecXi2], pw, m4);
+                        m4 = fma(x2, pw, m4);
                     }
                 }
             }
@@ -528,7 +546,10 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
         for (int ww = 1; ww < W; ++ww) sum += red[(ww * 5 + q) * kLanes + lane];
         M[q] = sum;
     }
-    cell_chain(d, M, out_lane, d.cell + c, pitch, sh.ser, sh.thr);
+    // the Maclaurin tables through scalar loads (uniform addresses, shared by
+    // every workgroup through the scalar cache)
+    using CP = const __attribute__((address_space(4))) double*;
+    cell_chain(d, M, out_lane, d.cell + c, pitch, (CP)d.tab.ser, (CP)d.tab.thr);
 }
 
 template <typename Tf, int STAGE, int W, int NV, int K>
