@@ -319,6 +319,24 @@ struct LoopLds {
     } u;
 };
 
+// A buffer resource over one velocity plane of a field (gfx9 resource word:
+// raw byte addressing, no format conversion, offsets range-checked against
+// the plane size), and binary32 / binary64 loads and stores through it.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* plane, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(plane), (short)0, bytes, 0x00020000);
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ T plane_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void plane_store(__amdgpu_buffer_rsrc_t r, uint32_t off, T x) {
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
+    else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, off, 0, 0);
+}
+
 // Legendre sums of the equilibrium coefficients at one angular node for
 // N_Omega = N: sum_m P_m(xi_J) c0_m and sum_m P_m(xi_J) c1_m, the record's
 // P_m and the cell's coefficient rows read in one batch.
@@ -405,14 +423,20 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
         }
     };
     const int hcl = lane < 5 ? hcc : cc;
+    // Loads and stores through a buffer resource per velocity plane (uniform
+    // base and size): per-lane 32-bit byte offsets, no 64-bit per-lane
+    // address arithmetic
+    // (a lane that stores owns cell c = cc, so its store offset is occ too)
+    const uint32_t occ = (uint32_t)cc * (uint32_t)sizeof(Tf), ohc = (uint32_t)hcl * (uint32_t)sizeof(Tf);
+    const int plane_bytes = (int)(pitch * sizeof(Tf));
     auto load_round = [&](const Pos& p, Tf (&a)[NV], Tf (&h)[NV], Tf (&n)[NV]) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             const int v = p.k * Q + min(p.jb + w + i * W, Q - 1);
-            const Tf* row = fcur + (size_t)v * pitch;
-            a[i] = row[cc];
-            h[i] = row[hcl];
-            if (STAGE > 1) n[i] = fn[(size_t)v * pitch + cc];
+            const auto row = plane_rsrc(fcur + (size_t)v * pitch, plane_bytes);
+            a[i] = plane_load<Tf>(row, occ);
+            h[i] = plane_load<Tf>(row, ohc);
+            if (STAGE > 1) n[i] = plane_load<Tf>(plane_rsrc(fn + (size_t)v * pitch, plane_bytes), occ);
         }
     };
     double gJ[NV], hJ[NV];   // Legendre sums of the coefficients at the wave's angular nodes
@@ -494,7 +518,7 @@ __device__ __forceinline__ void loop_tile(const InstDesc& d, int tile, LoopLds<T
                     if (out_lane) {
                         const Tf o = (Tf)out;
                         if (!isfinite(o)) bad |= 2u;
-                        fout[(size_t)v * pitch + c] = o;
+                        plane_store<Tf>(plane_rsrc(fout + (size_t)v * pitch, plane_bytes), occ, o);
                         // moments of the stored output (the next stage's field)
                         const double fo = (double)o, pw = pk * fo;
                         m0 += fo;
