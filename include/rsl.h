@@ -378,6 +378,50 @@ int rsl_mlp_tmunu(const double* m_lo, const double* m_hi, const float* y, int n,
  * solve. */
 int rsl_mlp_guard(const float* x, int n, const float* lo, const float* hi, unsigned* flag_dev, void* hip_stream);
 
+/* ------------------------------------------- velocity sets with azimuthal nodes
+ * For flows whose velocity is not along z (Sec. III D: the addition theorem
+ * of eq. leg_product and the azimuthal quadrature).  The set adds Q_phi
+ * equally spaced azimuths phi_l = 2 pi l / Q_phi with weights 2 pi / Q_phi to
+ * the Q_L radial and Q_xi polar nodes of rsl_make_quadrature; node
+ * v = (k Q_phi + l) Q_xi + j, direction Omega_v = (sin theta_j cos phi_l,
+ * sin theta_j sin phi_l, xi_j), momentum p_k = T0 pbar_k.  The equal-weight
+ * rule integrates trigonometric polynomials of degree below Q_phi exactly, so
+ * with Q_phi >= N_Omega + 3 the moments N^mu, T^{mu nu} of the truncated
+ * equilibrium are exact (the addition theorem makes P_m(cos gamma_u) a
+ * trigonometric polynomial of degree m in phi).  Q_phi = 1 is the aligned
+ * set of the paper (eq. pjk).  Tables live on the current HIP device. */
+typedef struct rsl_quad3 rsl_quad3;
+/* Limits: those of rsl_make_quadrature (N_L = 1) and 1 <= Q_phi <= 256.
+ * Errors: RSL_EINVAL, RSL_EUNSUPPORTED, RSL_EDEVICE; *out is NULL on error. */
+int rsl_make_quadrature3(int Q_L, int Q_xi, int Q_phi, int N_Omega, double T0, rsl_quad3** out);
+void rsl_free_quadrature3(rsl_quad3* q);
+/* Number of nodes V = Q_L Q_xi Q_phi, or RSL_EINVAL for a NULL set. */
+int rsl_quad3_velocities(const rsl_quad3* q);
+
+/* Discrete equilibrium of the truncated expansion (eq. feq_trunc, N_L = 1)
+ * for ncell cells at state_dev[c][5] = (n, T, u^x, u^y, u^z), u the spatial
+ * part of the four-velocity (gamma v), mapped by eq. fjk with the azimuthal
+ * weight 2 pi / Q_phi:
+ *   f_v = (w_j w_k / Q_phi) sum_m P_m(Omega_v . u_hat) (c0_m + L_1(pbar_k) c1_m)
+ * with the coefficients of the aligned flow at |u|.  Output f_dev[v][pitch]
+ * (binary64 or binary32 per dtype; cells c < ncell written, the rest of each
+ * row untouched).  Stream-ordered, asynchronous.  Errors: RSL_EINVAL (NULL
+ * buffers with ncell > 0, pitch < ncell, bad dtype, another device),
+ * RSL_EDEVICE.  ncell = 0 does nothing. */
+int rsl_feq3(const rsl_quad3* q, const double* state_dev, int ncell, int dtype, void* f_dev, int pitch,
+             void* hip_stream);
+
+/* Moments of f_dev[v][pitch] (eq. macro_jk over the set's nodes) and the
+ * Landau frame of T^{mu nu} (Sec. II E: T^{mu nu} u_nu = E u^mu, the timelike
+ * eigenvector; n = u_mu N^mu, P = E / 3, T = P / n).  Output
+ * out_dev[c][RSL_NMOM3] in the order below; the derived fields are NaN for a
+ * cell whose T^{mu nu} has no timelike eigenvector with E > 0 and n > 0.
+ * Stream-ordered, asynchronous.  Errors as rsl_feq3. */
+#define RSL_NMOM3 22   /* N^0..N^3, T^00 T^01 T^02 T^03 T^11 T^12 T^13 T^22 T^23 T^33,
+                          n, E, P, T, u^0, u^1, u^2, u^3 */
+int rsl_moments3(const rsl_quad3* q, const void* f_dev, int dtype, int ncell, int pitch, double* out_dev,
+                 void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

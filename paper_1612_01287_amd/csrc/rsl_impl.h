@@ -60,6 +60,16 @@ struct QuadDev {
                          // [rt][kk][lane] = K^P[16 rt + lane % 16][4 kk + lane / 16]
 };
 
+// Velocity sets with azimuthal nodes (vel3d.hip): device tables of one set.
+struct Quad3Dev {
+    const double* arec;   // [A][4]  Omega_x, Omega_y, Omega_z, w_j / Q_phi of angular node a = l Q_xi + j
+    const double* rrec;   // [QL][4] p_k, w_k, L_1(pbar_k), 0
+    const double* ser;    // the base set's Maclaurin tables
+    const double* thr;
+    int A, QL, NOm;
+    double T0, beta_series;
+};
+
 // Everything a kernel needs about one problem instance.  Passed by value as a
 // kernel argument for single-instance calls and stored in device arrays by
 // the batched path.
@@ -122,6 +132,14 @@ struct BatchLaunch {
 };
 
 }  // namespace rsl
+
+struct rsl_quad3 {
+    rsl_quad* base = nullptr;   // the polar and radial nodes, Maclaurin tables
+    int Qphi = 1, A = 0, V = 0;
+    int device = -1;
+    void* dmem = nullptr;       // angular and radial records
+    rsl::Quad3Dev dev{};
+};
 
 struct rsl_quad {
     int QL, Q, NOm, V;
@@ -190,5 +208,8 @@ int launch_bj_mfma(const InstDesc* descs, const int* groups, int ngroups, int QL
                    char* wbase, int nsteps, hipStream_t s);
 int launch_bj_steps(const InstDesc& d, double tau0, double dtau, int nsteps, hipStream_t s);
 int launch_bj_moments(const InstDesc& d, const void* f, double* out, int nf, hipStream_t s);
+
+int launch_feq3(const Quad3Dev& q, const double* state, int ncell, int dtype, void* f, int pitch, hipStream_t s);
+int launch_moments3(const Quad3Dev& q, const void* f, int dtype, int ncell, int pitch, double* out, hipStream_t s);
 
 }  // namespace rsl

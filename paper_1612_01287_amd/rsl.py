@@ -488,3 +488,58 @@ def guard(x, lo, hi, stream=None):
     flag = torch.zeros(1, dtype=torch.int32, device=x.device)
     check(_lib.rsl_mlp_guard(_p(x), x.shape[0], _p(lo), _p(hi), _p(flag), _stream(stream)))
     return int(flag.item()) != 0
+
+
+# ------------------------------------------- velocity sets with azimuthal nodes
+
+_sig("rsl_make_quadrature3", ctypes.c_int,
+     [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_vp)])
+_sig("rsl_free_quadrature3", None, [_vp])
+_sig("rsl_quad3_velocities", ctypes.c_int, [_vp])
+_sig("rsl_feq3", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp])
+_sig("rsl_moments3", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp])
+
+MOMENT3_FIELDS = ("N0", "N1", "N2", "N3", "T00", "T01", "T02", "T03", "T11", "T12", "T13", "T22", "T23", "T33",
+                  "n", "E", "P", "T", "u0", "u1", "u2", "u3")
+
+
+class Quadrature3:
+    """Velocity set with Q_phi azimuths (rsl_make_quadrature3; owned library handle)."""
+
+    def __init__(self, QL, Q, Qphi, NOm, T0=1.0):
+        h = _vp()
+        check(_lib.rsl_make_quadrature3(QL, Q, Qphi, NOm, float(T0), ctypes.byref(h)))
+        self._h = h
+        self.QL, self.Q, self.Qphi, self.NOm, self.T0 = QL, Q, Qphi, NOm, float(T0)
+        self.V = _lib.rsl_quad3_velocities(h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.rsl_free_quadrature3(h)
+            self._h = None
+
+
+def feq3(q3, state, dtype="f64", pitch=None, out=None, stream=None):
+    """[V, pitch] equilibrium populations of the [ncell, 5] fp64 device states
+    (n, T, u^x, u^y, u^z); rsl_feq3."""
+    ncell = state.shape[0]
+    pitch = ncell if pitch is None else pitch
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if out is None:
+        out = torch.zeros((q3.V, pitch), dtype=tdt, device=state.device)
+    check(_lib.rsl_feq3(q3.handle, _p(state), ncell, C["RSL_F64"] if dtype == "f64" else C["RSL_F32"], _p(out),
+                        pitch, _stream(stream)))
+    return out
+
+
+def moments3(q3, f, ncell, stream=None):
+    """[ncell, RSL_NMOM3] moments and Landau frame of the [V, pitch] populations f; rsl_moments3."""
+    out = torch.empty((ncell, C["RSL_NMOM3"]), dtype=torch.float64, device=f.device)
+    dt = C["RSL_F64"] if f.dtype == torch.float64 else C["RSL_F32"]
+    check(_lib.rsl_moments3(q3.handle, _p(f), dt, ncell, f.shape[1], _p(out), _stream(stream)))
+    return out

@@ -30,3 +30,8 @@ def smooth_perturbation(V, nz, seed, amp=0.05):
         ph = rng.uniform(0, 2 * np.pi, size=(V, 1))
         out += amp * a * np.sin(2 * np.pi * m * z[None, :] + ph) / m
     return out
+
+
+def rng(seed):
+    """The seeded generator every synthetic input of the tests draws from."""
+    return np.random.default_rng(seed)
