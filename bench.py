@@ -31,7 +31,11 @@ Prints one JSON line.  Its "aux" object carries further measurements:
   learned  the learned T^{mu nu} correction (training on 2.1e7 samples from
            2048 paired runs at N_z = 2048, evaluation on 64 instances);
   learned_c5 (only on request) the learned correction evaluated at full
-           size: 512 instances x N_z = 8192 against R-SLB(4;128).
+           size: 512 instances x N_z = 8192 against R-SLB(4;128);
+  vel3d    a velocity set with azimuthal nodes (Q_L = 3, Q_xi = 16, Q_phi = 8,
+           N_Omega = 4: 384 nodes) over 2^20 cells of seeded states moving in
+           any direction: the equilibrium written (rsl_feq3) and the moments
+           with the Landau frame read back (rsl_moments3), binary32.
 The oracle (plain C) is timed on the host's cores on a bounded sample of the
 headline workload ("cpu_baseline"), and single-threaded beside each aux leg.
 """
@@ -80,7 +84,7 @@ def parse(argv=None):
                     help="comma-separated stage-kernel variant per velocity class (-1: empty), and an eighth "
                          "for the whole batch as one class (-1: per class); skips the autotuner")
     ap.add_argument("--aux", default="all",
-                    choices=("none", "all", "sweep", "c1", "bjorken", "scaled", "learned", "learned_c5"),
+                    choices=("none", "all", "sweep", "c1", "bjorken", "scaled", "learned", "learned_c5", "vel3d"),
                     help="also measure the aux legs (all: every one but learned_c5), or one of them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy five times (the reference kernel for "
@@ -442,6 +446,69 @@ def bjorken_leg(torch, rsl, stream, n=4096, window=1000, seed=3, cpu=True):
     return out
 
 
+def vel3d_states(ncell, seed=7):
+    """(ncell, 5) rows (n, T, u^x, u^y, u^z): n, T uniform in [0.3, 2], fluid
+    directions uniform on the sphere, |beta| uniform in [0, 0.9]."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    n, T = rng.uniform(0.3, 2.0, ncell), rng.uniform(0.3, 2.0, ncell)
+    d = rng.normal(size=(ncell, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    beta = rng.uniform(0.0, 0.9, ncell)
+    return np.column_stack([n, T, d * (beta / np.sqrt(1.0 - beta * beta))[:, None]])
+
+
+def vel3d_leg(torch, rsl, stream, ncell=1 << 20, reps=20, cpu=True):
+    """rsl_feq3 (bytes: V binary32 values written and 40 B of state read per
+    cell) and rsl_moments3 (V values read, 176 B written per cell), HIP events
+    over `reps` launches each."""
+    QL, Q, Qphi, NOm = 3, 16, 8, 4
+    q3 = rsl.Quadrature3(QL, Q, Qphi, NOm)
+    S = vel3d_states(ncell)
+    st = torch.tensor(S, device="cuda")
+    f = torch.empty((q3.V, ncell), dtype=torch.float32, device="cuda")
+    rsl.feq3(q3, st, "f32", out=f, stream=stream)
+    m = rsl.moments3(q3, f, ncell, stream=stream)
+    stream.synchronize()
+    t_feq = _events(torch, stream, lambda: rsl.feq3(q3, st, "f32", out=f, stream=stream), reps) / reps
+    out_m = torch.empty_like(m)
+    t_mom = _events(torch, stream, lambda: _lib_moments3(rsl, q3, f, ncell, out_m, stream), reps) / reps
+    mh = out_m.cpu().numpy()
+    import numpy as np
+    rec_err = float(np.max(np.abs(mh[:, 14] - S[:, 0]) / S[:, 0]))
+    b_feq = ncell * (q3.V * 4.0 + 40.0)
+    b_mom = ncell * (q3.V * 4.0 + 8.0 * rsl.C["RSL_NMOM3"])
+    gf, gm = b_feq / t_feq / 1e9, b_mom / t_mom / 1e9
+    out = {"workload": "velocity set with azimuthal nodes: Q_L = 3, Q_xi = 16, Q_phi = 8, N_Omega = 4 (384 nodes), "
+                       "2^20 cells, fluid directions uniform on the sphere, |beta| <= 0.9, f32",
+           "value": ncell * q3.V / t_feq, "unit": "equilibrium populations/s",
+           "feq3_us": round(t_feq * 1e6, 1), "moments3_us": round(t_mom * 1e6, 1),
+           "moments3_values_per_s": ncell * q3.V / t_mom,
+           "density_round_trip_rel_err": rec_err,
+           "roofline": {"bound": "hbm", "achieved": round(gf, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gf / HBM_PEAK_GBS, 4),
+                        "kernel": "feq3_kernel<float> (384 x 4 B written + 40 B read per cell)",
+                        "moments3": {"achieved": round(gm, 1), "frac": round(gm / HBM_PEAK_GBS, 4),
+                                     "kernel": "moments3_kernel<float> (384 x 4 B read + 176 B written per cell)"}}}
+    if cpu:
+        from oracle import vel3d
+        vs = vel3d.VelocitySet3(QL, Q, Qphi, NOm)
+        nsamp = 2000
+        out["cpu_baseline"] = _oracle_rate(lambda: [vel3d.feq3(vs, *S[c, :2], S[c, 2:]) for c in range(nsamp)],
+                                           nsamp * q3.V,
+                                           "the oracle's equilibrium for the first %d cells (numpy, one core)"
+                                           % nsamp)
+        out["cpu_baseline"]["unit"] = "equilibrium populations/s"
+    return out
+
+
+def _lib_moments3(rsl, q3, f, ncell, out, stream):
+    import ctypes
+    rsl.check(rsl.lib().rsl_moments3(q3.handle, ctypes.c_void_p(f.data_ptr()), rsl.C["RSL_F32"], ncell,
+                                     f.shape[1], ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(stream.cuda_stream)))
+
+
 def learned_leg(torch, stream, n_runs=2048, nz_train=2048, n_inst=64, nz_eval=2048, epochs=100, chunk=None):
     from paper_1612_01287_amd import learned
     t0 = time.perf_counter()
@@ -552,6 +619,7 @@ def main():
                 "bjorken": lambda: bjorken_leg(torch, rsl, stream, cpu=cpu),
                 "scaled": lambda: scaled_leg(torch, rsl, stream),
                 "learned": lambda: learned_leg(torch, stream),
+                "vel3d": lambda: vel3d_leg(torch, rsl, stream, cpu=cpu),
                 "learned_c5": lambda: learned_leg(torch, stream, n_runs=512, nz_train=8192, n_inst=512,
                                                   nz_eval=8192, epochs=100, chunk=128)}
         del B

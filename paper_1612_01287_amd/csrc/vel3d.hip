@@ -42,6 +42,14 @@ __global__ void __launch_bounds__(kV3Threads) feq3_kernel(const double* __restri
     const int nt = series_terms_uniform(wave_max_uniform(fmin(beta * beta, beta_s * beta_s)), thr);
     double c0[kMaxNOm + 1], c1[kMaxNOm + 1];
     feq_coef(n, T, beta, gam, T0, NOm, beta_s, ser, nt, c0, c1);
+    // radial weights and L_1 values, loaded once (Q_L <= 8)
+    double wk[8], lk[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        wk[k] = k < QL ? rrec[4 * k + 1] : 0.0;
+        lk[k] = k < QL ? rrec[4 * k + 2] : 0.0;
+    }
+#pragma unroll 2
     for (int a = 0; a < A; ++a) {
         CP r = arec + 4 * (size_t)a;
         const double x = r[0] * hx + r[1] * hy + r[2] * hz, wa = r[3];
@@ -62,10 +70,12 @@ __global__ void __launch_bounds__(kV3Threads) feq3_kernel(const double* __restri
                 h = fma(pn, c1[m + 1], h);
             }
         }
-        for (int k = 0; k < QL; ++k) {
-            CP rk = rrec + 4 * k;
-            const double fv = wa * rk[1] * fma(rk[2], h, g);
-            if (live) f[((size_t)k * A + a) * pitch + cell] = (Tf)fv;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k < QL) {
+                const double fv = wa * wk[k] * fma(lk[k], h, g);
+                if (live) f[((size_t)k * A + a) * pitch + cell] = (Tf)fv;
+            }
         }
     }
 }
@@ -153,10 +163,12 @@ __global__ void __launch_bounds__(kV3Threads) moments3_kernel(const Tf* __restri
     if (cell >= ncell) return;
     double N[4] = {0.0, 0.0, 0.0, 0.0};
     double M[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // plane by plane (radial node outer): consecutive loads walk neighbouring
+    // velocity rows of one plane
     for (int k = 0; k < QL; ++k) {
         const double p = rrec[4 * k];
         const Tf* fk = f + (size_t)k * A * pitch + cell;
-#pragma unroll 4
+#pragma unroll 8
         for (int a = 0; a < A; ++a) {
             CP r = arec + 4 * (size_t)a;
             const double ox = r[0], oy = r[1], oz = r[2];
