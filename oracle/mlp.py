@@ -110,3 +110,58 @@ def adam_step(P, G, state, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         vh = v / (1 - b2 ** t)
         P[k] = P[k] - lr * mh / (np.sqrt(vh) + eps)
     return P
+
+
+# ---------------------------------------------------------------- in-loop feedback
+#
+# Feeding a correction of the moments back into the populations.  A change of
+# (T^00, T^0z, T^zz) is taken in the span of the three population vectors
+#     b_c[v] = w_j w_k L^(2)_1(pbar_k) xi_j^c,      c = 0, 1, 2  (v = k Q + j)
+# (no N^0, N^z: the Laguerre rule gives sum_k w_k (3 - pbar_k) = 0), a change
+# of (N^0, N^z) in the span of
+#     b'_c[v] = w_j w_k (4 - pbar_k) xi_j^c,        c = 0, 1
+# (no T^{mu nu}: sum_k w_k pbar_k (4 - pbar_k) = 0).  The coefficients solve
+# the moment equations written out as a 5 x 5 system (rows N^0, N^z, T^00,
+# T^0z, T^zz of each vector) by least squares.
+
+def _basis(vs):
+    xi = np.tile(vs.xi, vs.QL)
+    w = np.outer(vs.wL, vs.wxi).ravel()
+    L1 = np.repeat(3.0 - vs.pb, vs.Q)
+    G0 = np.repeat(4.0 - vs.pb, vs.Q)
+    return np.stack([w * L1 * xi ** c for c in range(3)] + [w * G0 * xi ** c for c in range(2)], axis=1)
+
+
+def _moment_rows(vs):
+    """(5, V): N^0, N^z, T^00, T^0z, T^zz weights of each population."""
+    xi = np.tile(vs.xi, vs.QL)
+    p = np.repeat(vs.pb * vs.T0, vs.Q)
+    return np.stack([np.ones_like(xi), xi, p, p * xi, p * xi * xi])
+
+
+def inject(vs, f, dT, dN=None):
+    """f + df with moments(df) = (dN, dT) per cell (dN = 0 if None); f [V, nz],
+    dT [nz, 3], dN [nz, 2]."""
+    nz = dT.shape[0]
+    B = _basis(vs)
+    A = _moment_rows(vs) @ B                                                # (5, 5)
+    dN = np.zeros((nz, 2)) if dN is None else np.asarray(dN, dtype=np.float64)
+    rhs = np.concatenate([dN.T, np.asarray(dT, dtype=np.float64).T])
+    coef, *_ = np.linalg.lstsq(A, rhs, rcond=None)                          # (5, nz)
+    return np.asarray(f, dtype=np.float64) + B @ coef
+
+
+def project(vs_hi, f_hi, vs_lo):
+    """Low-order populations with the N^mu and T^{mu nu} of f_hi [V_hi, nz]:
+    the low-order equilibrium of f_hi's Landau frame plus the change that
+    carries the rest of both."""
+    from . import feq, landau
+    R_hi, R_lo = _moment_rows(vs_hi), _moment_rows(vs_lo)
+    M = R_hi @ np.asarray(f_hi, dtype=np.float64)                           # (5, nz)
+    nz = M.shape[1]
+    out = np.zeros((vs_lo.V, nz))
+    for s in range(nz):
+        L = landau(M[:, s])
+        out[:, s] = feq(vs_lo, L["n"], L["T"], L["beta"])
+    D = M - R_lo @ out
+    return inject(vs_lo, out, D[2:].T, D[:2].T)
