@@ -373,6 +373,26 @@ int rsl_mlp_adam(float* params, const float* grad, float* m, float* v, unsigned 
  * mode 1: t_corr[n][3] = T_lo + y T^00_lo (corrected T^00, T^0z, T^zz). */
 int rsl_mlp_tmunu(const double* m_lo, const double* m_hi, const float* y, int n, int mode, float* t_out,
                   double* t_corr, void* hip_stream);
+/* In-loop feedback of the correction: adds to every cell s of one Sod
+ * instance's f the population change
+ *   df_jk = w_j w_k L_1^(2)(pbar_k) (a0 + a1 xi_j + a2 xi_j^2),
+ * which leaves N^0 and N^z unchanged (the Laguerre rule gives
+ * sum_k w_k L_1(pbar_k) = 0) and moves (T^00, T^0z, T^zz) by y[s][0..2] times
+ * the cell's T^00 (the network's output convention); (a0, a1, a2) solve the
+ * three moment equations.  In place, stream-ordered.  RSL_EINVAL for NULL
+ * pointers or a non-Sod problem; RSL_EUNSUPPORTED when Q_xi < 3 (the three
+ * moment equations are then singular). */
+int rsl_mlp_inject(const rsl_quad* q, const rsl_problem* p, void* f_dev, const float* y, void* hip_stream);
+/* Projection of a high-order Sod state onto a low-order velocity set over the
+ * same cells: f_lo = the low-order equilibrium (eq. feq_trunc) of f_hi's
+ * Landau frame (eqs. E_landau, u_landau), plus the change along the basis
+ * above and along w_j w_k (4 - pbar_k) xi_j^c (c = 0, 1; no T^{mu nu}) that
+ * gives f_lo the N^0, N^z, T^00, T^0z, T^zz of f_hi.  A cell without a
+ * Landau frame gets NaN populations.  Either dtype on either side.
+ * Stream-ordered.  RSL_EINVAL for NULL pointers, non-Sod problems or
+ * different nz; RSL_EUNSUPPORTED as rsl_mlp_inject for q_lo. */
+int rsl_project(const rsl_quad* q_hi, const rsl_problem* p_hi, const void* f_hi, const rsl_quad* q_lo,
+                const rsl_problem* p_lo, void* f_lo, void* hip_stream);
 /* Sets *flag_dev (atomic OR 1) if any feature lies outside [lo[c], hi[c]]
  * (the range seen in training): the caller then falls back to the high-order
  * solve. */

@@ -13,6 +13,8 @@
 //   D (16 x 16, f32):             lane l holds D[4 (l / 16) + r][l % 16], r = 0..3
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <mutex>
 
@@ -395,6 +397,139 @@ __global__ void guard_kernel(const float* __restrict__ x, int n, const float* __
     if (out) atomicOr(flag, 1u);
 }
 
+// In-loop feedback.  A change of (T^00, T^0z, T^zz) goes along
+//   b_c[v] = w_j w_k L_1(pbar_k) xi_j^c (c = 0, 1, 2), which carries no N^0, N^z,
+// a change of (N^0, N^z) along
+//   b'_c[v] = w_j w_k (4 - pbar_k) xi_j^c (c = 0, 1), which carries no T^{mu nu};
+// tinv, ninv invert the moment matrices of the two families (per velocity set).
+struct InjectConst {
+    double tinv[9], ninv[4];
+};
+
+// f += df with (dT^00, dT^0z, dT^zz) = y T^00 per cell (the network's output
+// convention), T^00 the cell's own.
+template <typename Tf>
+__global__ void __launch_bounds__(TPB) inject_kernel(InstDesc d, Tf* __restrict__ f, const float* __restrict__ y,
+                                                     InjectConst K) {
+    const int s = blockIdx.x * TPB + threadIdx.x;
+    if (s >= d.nz) return;
+    double e = 0.0;
+    for (int v = 0; v < d.V; ++v) e = fma(d.tab.pv[v], (double)f[(size_t)v * d.pitch + s], e);
+    const double dT[3] = {y[3 * (size_t)s] * e, y[3 * (size_t)s + 1] * e, y[3 * (size_t)s + 2] * e};
+    double a[3];
+    for (int r = 0; r < 3; ++r) a[r] = K.tinv[3 * r] * dT[0] + K.tinv[3 * r + 1] * dT[1] + K.tinv[3 * r + 2] * dT[2];
+    for (int v = 0; v < d.V; ++v) {
+        const double x = d.tab.xv[v];
+        const double df = d.tab.wxw[v] * d.tab.l1v[v] * fma(fma(a[2], x, a[1]), x, a[0]);
+        Tf& fv = f[(size_t)v * d.pitch + s];
+        fv = (Tf)((double)fv + df);
+    }
+}
+
+// Low-order populations fl with the N^mu, T^{mu nu} of the high-order fh (same
+// cells): the low-order equilibrium of fh's Landau frame (eqs. E_landau,
+// u_landau, feq_trunc) as stored, plus the change along b and b' that carries
+// the rest of both.  NaN populations for a cell without a Landau frame.
+template <typename Th, typename Tl>
+__global__ void __launch_bounds__(TPB) project_kernel(InstDesc dh, const Th* __restrict__ fh, InstDesc dl,
+                                                      Tl* __restrict__ fl, InjectConst K) {
+    const int s = blockIdx.x * TPB + threadIdx.x;
+    if (s >= dl.nz) return;
+    double M[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < dh.V; ++v) {
+        const double fv = (double)fh[(size_t)v * dh.pitch + s];
+        const double x = dh.tab.xv[v], pf = dh.tab.pv[v] * fv;
+        M[0] += fv;
+        M[1] = fma(x, fv, M[1]);
+        M[2] += pf;
+        M[3] = fma(x, pf, M[3]);
+        M[4] = fma(x * x, pf, M[4]);
+    }
+    const CellState cs = landau(M[0], M[1], M[2], M[3], M[4]);
+    if (!cs.ok) {
+        for (int v = 0; v < dl.V; ++v) fl[(size_t)v * dl.pitch + s] = (Tl)__builtin_nan("");
+        return;
+    }
+    const int nt = series_terms(fmin(cs.beta * cs.beta, dl.beta_series * dl.beta_series), dl.tab.thr);
+    double c0[kMaxNOm + 1], c1[kMaxNOm + 1];
+    feq_coef(cs.n, cs.T, cs.beta, cs.gamma, dl.T0, dl.NOm, dl.beta_series, dl.tab.ser, nt, c0, c1);
+    double E[5] = {0.0, 0.0, 0.0, 0.0, 0.0};     // moments of the stored equilibrium
+    for (int v = 0; v < dl.V; ++v) {
+        double g = 0.0, h = 0.0;
+        for (int m = 0; m <= dl.NOm; ++m) {
+            const double P = dl.tab.Pv[(size_t)m * dl.V + v];
+            g = fma(P, c0[m], g);
+            h = fma(P, c1[m], h);
+        }
+        const Tl fe = (Tl)(dl.tab.wxw[v] * fma(dl.tab.l1v[v], h, g));
+        fl[(size_t)v * dl.pitch + s] = fe;
+        const double fd = (double)fe, x = dl.tab.xv[v], pf = dl.tab.pv[v] * fd;
+        E[0] += fd;
+        E[1] = fma(x, fd, E[1]);
+        E[2] += pf;
+        E[3] = fma(x, pf, E[3]);
+        E[4] = fma(x * x, pf, E[4]);
+    }
+    const double dN[2] = {M[0] - E[0], M[1] - E[1]}, dT[3] = {M[2] - E[2], M[3] - E[3], M[4] - E[4]};
+    double a[3], b[2];
+    for (int r = 0; r < 3; ++r) a[r] = K.tinv[3 * r] * dT[0] + K.tinv[3 * r + 1] * dT[1] + K.tinv[3 * r + 2] * dT[2];
+    for (int r = 0; r < 2; ++r) b[r] = K.ninv[2 * r] * dN[0] + K.ninv[2 * r + 1] * dN[1];
+    for (int v = 0; v < dl.V; ++v) {
+        const double x = dl.tab.xv[v], pb = dl.tab.pv[v] / dl.T0;
+        const double df = dl.tab.wxw[v] * (dl.tab.l1v[v] * fma(fma(a[2], x, a[1]), x, a[0]) +
+                                           (4.0 - pb) * fma(b[1], x, b[0]));
+        Tl& fv = fl[(size_t)v * dl.pitch + s];
+        fv = (Tl)((double)fv + df);
+    }
+}
+
+// The two moment matrices of a velocity set (from its host tables), inverted.
+int inject_const(const rsl_quad* q, InjectConst* K) {
+    double S[5] = {0.0, 0.0, 0.0, 0.0, 0.0};          // sum_j w_j xi_j^r, r = 0..4
+    for (int j = 0; j < q->Q; ++j) {
+        double xr = 1.0;
+        for (int r = 0; r < 5; ++r) {
+            S[r] += q->wxi[j] * xr;
+            xr *= q->xi[j];
+        }
+    }
+    double G1 = 0.0, H0 = 0.0;                        // sum_k w_k p_k L_1, sum_k w_k (4 - pbar_k)
+    for (int k = 0; k < q->QL; ++k) {
+        G1 += q->wL[k] * q->T0 * q->pbar[k] * (3.0 - q->pbar[k]);
+        H0 += q->wL[k] * (4.0 - q->pbar[k]);
+    }
+    // T block: rows (T^00, T^0z, T^zz) = G1 (S_c, S_{c+1}, S_{c+2}) for b_c
+    double A[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) A[r][c] = G1 * S[r + c];
+    const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                       A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                       A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    // N block: rows (N^0, N^z) = H0 (S_c, S_{c+1}) for b'_c
+    const double n00 = H0 * S[0], n01 = H0 * S[1], n11 = H0 * S[2];
+    const double detn = n00 * n11 - n01 * n01;
+    // singular when the polar rule cannot tell 1, xi, xi^2 apart (Q_xi < 3):
+    // the determinants vanish to rounding relative to their diagonals
+    if (!(fabs(det) > 1e-9 * fabs(A[0][0] * A[1][1] * A[2][2])) || !(fabs(detn) > 1e-9 * fabs(n00 * n11)) ||
+        !std::isfinite(det) || !std::isfinite(detn))
+        return set_error(RSL_EUNSUPPORTED, "the feedback basis is singular for this velocity set (need Q_xi >= 3)");
+    const double id = 1.0 / det;
+    K->tinv[0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) * id;
+    K->tinv[1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+    K->tinv[2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+    K->tinv[3] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) * id;
+    K->tinv[4] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+    K->tinv[5] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+    K->tinv[6] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) * id;
+    K->tinv[7] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
+    K->tinv[8] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+    K->ninv[0] = n11 / detn;
+    K->ninv[1] = -n01 / detn;
+    K->ninv[2] = -n01 / detn;
+    K->ninv[3] = n00 / detn;
+    return RSL_OK;
+}
+
 constexpr size_t kFwdLds = sizeof(WL) + sizeof(AL);
 constexpr size_t kBwdLds = sizeof(WL) + sizeof(BL);
 
@@ -468,6 +603,53 @@ int rsl_mlp_features(const rsl_quad* q, const rsl_problem* p, const void* f_dev,
         hipLaunchKernelGGL(features_kernel<float>, grid, dim3(TPB), 0, s, d, (const float*)f_dev, log_tau,
                            shift_dev, scale_dev, feat_dev);
     return hip_check(hipGetLastError(), "features_kernel launch");
+}
+
+int rsl_mlp_inject(const rsl_quad* q, const rsl_problem* p, void* f_dev, const float* y, void* hip_stream) {
+    if (!q || !p || !f_dev || !y) return set_error(RSL_EINVAL, "null argument");
+    if (!q->on_device) return set_error(RSL_EINVAL, "rsl_quad was built with RSL_QUAD_HOST_ONLY");
+    if (p->problem != RSL_SOD) return set_error(RSL_EINVAL, "the feedback is defined for Sod instances");
+    InjectConst K;
+    int rc = inject_const(q, &K);
+    if (rc) return rc;
+    InstDesc d = make_desc(q, p, f_dev, f_dev, 0.0);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const dim3 grid((p->nz + TPB - 1) / TPB);
+    if (p->dtype == RSL_F64)
+        hipLaunchKernelGGL(inject_kernel<double>, grid, dim3(TPB), 0, s, d, (double*)f_dev, y, K);
+    else
+        hipLaunchKernelGGL(inject_kernel<float>, grid, dim3(TPB), 0, s, d, (float*)f_dev, y, K);
+    return hip_check(hipGetLastError(), "inject_kernel launch");
+}
+
+int rsl_project(const rsl_quad* q_hi, const rsl_problem* p_hi, const void* f_hi, const rsl_quad* q_lo,
+                const rsl_problem* p_lo, void* f_lo, void* hip_stream) {
+    if (!q_hi || !p_hi || !f_hi || !q_lo || !p_lo || !f_lo) return set_error(RSL_EINVAL, "null argument");
+    if (!q_hi->on_device || !q_lo->on_device) return set_error(RSL_EINVAL, "rsl_quad was built with RSL_QUAD_HOST_ONLY");
+    if (p_hi->problem != RSL_SOD || p_lo->problem != RSL_SOD)
+        return set_error(RSL_EINVAL, "the projection is defined for Sod instances");
+    if (p_hi->nz != p_lo->nz) return set_error(RSL_EINVAL, "the two instances must have the same cells");
+    InjectConst K;
+    int rc = inject_const(q_lo, &K);
+    if (rc) return rc;
+    InstDesc dh = make_desc(q_hi, p_hi, (void*)f_hi, (void*)f_hi, 0.0);
+    InstDesc dl = make_desc(q_lo, p_lo, f_lo, f_lo, 0.0);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const dim3 grid((p_lo->nz + TPB - 1) / TPB);
+    const bool h64 = p_hi->dtype == RSL_F64, l64 = p_lo->dtype == RSL_F64;
+    if (h64 && l64)
+        hipLaunchKernelGGL((project_kernel<double, double>), grid, dim3(TPB), 0, s, dh, (const double*)f_hi, dl,
+                           (double*)f_lo, K);
+    else if (h64)
+        hipLaunchKernelGGL((project_kernel<double, float>), grid, dim3(TPB), 0, s, dh, (const double*)f_hi, dl,
+                           (float*)f_lo, K);
+    else if (l64)
+        hipLaunchKernelGGL((project_kernel<float, double>), grid, dim3(TPB), 0, s, dh, (const float*)f_hi, dl,
+                           (double*)f_lo, K);
+    else
+        hipLaunchKernelGGL((project_kernel<float, float>), grid, dim3(TPB), 0, s, dh, (const float*)f_hi, dl,
+                           (float*)f_lo, K);
+    return hip_check(hipGetLastError(), "project_kernel launch");
 }
 
 int rsl_mlp_to_bf16(const float* params, unsigned short* params_bf16, void* hip_stream) {

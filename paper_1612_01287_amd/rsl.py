@@ -543,3 +543,21 @@ def moments3(q3, f, ncell, stream=None):
     dt = C["RSL_F64"] if f.dtype == torch.float64 else C["RSL_F32"]
     check(_lib.rsl_moments3(q3.handle, _p(f), dt, ncell, f.shape[1], _p(out), _stream(stream)))
     return out
+
+
+# ------------------------------------------------------ in-loop feedback
+
+_sig("rsl_mlp_inject", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _vp])
+_sig("rsl_project", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, ctypes.POINTER(Problem), _vp, _vp])
+
+
+def inject(quad, problem, f_buf, y, stream=None):
+    """Adds the population change that moves (T^00, T^0z, T^zz) by y * T^00
+    ([nz, 3] fp32 device) to one Sod instance's f, in place; rsl_mlp_inject."""
+    check(_lib.rsl_mlp_inject(quad.handle, ctypes.byref(problem), _p(f_buf), _p(y), _stream(stream)))
+
+
+def project(q_hi, p_hi, f_hi, q_lo, p_lo, f_lo, stream=None):
+    """f_lo <- the low-order state with f_hi's N^mu and T^{mu nu}; rsl_project."""
+    check(_lib.rsl_project(q_hi.handle, ctypes.byref(p_hi), _p(f_hi), q_lo.handle, ctypes.byref(p_lo), _p(f_lo),
+                           _stream(stream)))
