@@ -32,6 +32,9 @@ Prints one JSON line.  Its "aux" object carries further measurements:
            2048 paired runs at N_z = 2048, evaluation on 64 instances);
   learned_c5 (only on request) the learned correction evaluated at full
            size: 512 instances x N_z = 8192 against R-SLB(4;128);
+  learned_inloop (only on request) the correction fed back into the
+           low-order populations every 0.05 (rsl_mlp_inject), trained on
+           teacher-forced runs, judged against R-SLB(4;128);
   vel3d    a velocity set with azimuthal nodes (Q_L = 3, Q_xi = 16, Q_phi = 8,
            N_Omega = 4: 384 nodes) over 2^20 cells of seeded states moving in
            any direction: the equilibrium written (rsl_feq3) and the moments
@@ -84,8 +87,9 @@ def parse(argv=None):
                     help="comma-separated stage-kernel variant per velocity class (-1: empty), and an eighth "
                          "for the whole batch as one class (-1: per class); skips the autotuner")
     ap.add_argument("--aux", default="all",
-                    choices=("none", "all", "sweep", "c1", "bjorken", "scaled", "learned", "learned_c5", "vel3d"),
-                    help="also measure the aux legs (all: every one but learned_c5), or one of them")
+                    choices=("none", "all", "sweep", "c1", "bjorken", "scaled", "learned", "learned_c5", "vel3d",
+                             "learned_inloop"),
+                    help="also measure the aux legs (all: every one but learned_c5 and learned_inloop), or one of them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy five times (the reference kernel for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -502,6 +506,27 @@ def vel3d_leg(torch, rsl, stream, ncell=1 << 20, reps=20, cpu=True):
     return out
 
 
+def learned_inloop_leg(torch, stream, n_runs=2048, nz=2048, n_inst=64, interval=0.05, n_intervals=5, epochs=100):
+    from paper_1612_01287_amd import learned
+    t0 = time.perf_counter()
+    prog = lambda msg: _progress("learned_inloop: " + msg)
+    X, T = learned.generate_inloop(n_runs=n_runs, nz=nz, interval=interval, n_intervals=n_intervals, seed=5, q_lo=8,
+                                   q_hi=128, chunk=512)
+    _progress("learned_inloop: %d training samples generated (%.1f s)" % (X.shape[0], time.perf_counter() - t0))
+    corr, hist = learned.train(X, T, epochs=epochs, batch=8192, lr=2e-3, seed=1, margin=0.25, progress=prog)
+    del X, T
+    torch.cuda.empty_cache()
+    res = learned.evaluate_inloop(corr, n_inst=n_inst, nz=nz, interval=interval, n_intervals=n_intervals, seed=6,
+                                  q_lo=8, q_hi=128, progress=prog)
+    out = {"workload": "learned T^{mu nu} correction fed back into f every %g (%d times): R-SLB(4;8) + network vs "
+                       "R-SLB(4;128), %d instances, N_z = %d, t = %g; trained on %d teacher-forced runs at N_z = %d"
+                       % (interval, n_intervals, n_inst, nz, interval * n_intervals, n_runs, nz),
+           "train_and_data_s": time.perf_counter() - t0, "final_loss_scaled": hist[-1]}
+    out.update(res)
+    out["speedup_vs_plain"] = res["t_high_order_s"] / res["t_learned_s"]
+    return out
+
+
 def _lib_moments3(rsl, q3, f, ncell, out, stream):
     import ctypes
     rsl.check(rsl.lib().rsl_moments3(q3.handle, ctypes.c_void_p(f.data_ptr()), rsl.C["RSL_F32"], ncell,
@@ -620,6 +645,7 @@ def main():
                 "scaled": lambda: scaled_leg(torch, rsl, stream),
                 "learned": lambda: learned_leg(torch, stream),
                 "vel3d": lambda: vel3d_leg(torch, rsl, stream, cpu=cpu),
+                "learned_inloop": lambda: learned_inloop_leg(torch, stream),
                 "learned_c5": lambda: learned_leg(torch, stream, n_runs=512, nz_train=8192, n_inst=512,
                                                   nz_eval=8192, epochs=100, chunk=128)}
         del B
@@ -627,7 +653,7 @@ def main():
         out["aux"] = {}
         with torch.cuda.stream(stream):
             for k, fn in legs.items():
-                if a.aux == k or (a.aux == "all" and k != "learned_c5"):
+                if a.aux == k or (a.aux == "all" and k not in ("learned_c5", "learned_inloop")):
                     t0 = time.perf_counter()
                     out["aux"][k] = fn()
                     torch.cuda.empty_cache()

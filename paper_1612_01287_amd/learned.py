@@ -41,7 +41,7 @@ class PairedEnsemble:
         self.q_lo, self.q_hi = q_lo, q_hi
         self.dt = 0.5 / nz
         self.batches = {}
-        for Q in (q_lo, q_hi):
+        for Q in dict.fromkeys((q_lo, q_hi)):
             probs = [rsl.make_problem(nz=nz, dtype=dtype, bc="outflow", tau_r=tau, nL=1.0, TL=1.0, nR=nR, TR=TR)
                      for (TR, nR, tau) in states]
             B = rsl.Batch([self.quads[Q]] * len(states), probs, [self.dt] * len(states))
@@ -228,3 +228,96 @@ def evaluate(corr, n_inst, nz, t_end, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=
         out["features_outside"] = corr.outside(X)
     out["err_corrected"] = rel(Tc) if Tc is not None else None
     return out
+
+
+# ------------------------------------------------------------ in-loop feedback
+#
+# The correction fed back through f instead of applied to the output: every
+# `interval` of time the low-order state's features give the network's
+# (T_hi - T_lo) / T^00_lo, and rsl_mlp_inject moves the state's T^00, T^0z,
+# T^zz by that much (N^mu unchanged).  Training pairs come from the same loop
+# with the true defect in place of the network's (teacher forcing): both sets
+# advance one interval, the pair is (features of the low-order state, the
+# high-order minus low-order T^{mu nu}), and that defect is injected into the
+# low-order state before the next interval, so the training states are the
+# corrected low-order states inference meets.
+
+def _inject_all(ens, y, stream=None):
+    Bl, ql = ens.batches[ens.q_lo], ens.quads[ens.q_lo]
+    nz = ens.nz
+    for i in range(Bl.n):
+        rsl.inject(ql, Bl.problems[i], Bl.f(i), y[i * nz:(i + 1) * nz].contiguous(), stream=stream)
+
+
+def generate_inloop(n_runs, nz, interval, n_intervals, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=128, dtype="f32",
+                    progress=None, chunk=None):
+    """Features X [N, 81] of the teacher-forced low-order states at the end of
+    each interval and the defects T [N, 3] there."""
+    rng = np.random.default_rng(seed)
+    states = _states(rng, n_runs, *tau_range)
+    chunk = chunk or n_runs
+    X, T = [], []
+    for c0 in range(0, n_runs, chunk):
+        ens = PairedEnsemble(states[c0:c0 + chunk], nz, q_lo, q_hi, dtype)
+        k = int(round(interval / ens.dt))
+        for it in range(n_intervals):
+            ens.advance(k)
+            X.append(ens.features())
+            T.append(rsl.tmunu_targets(ens.moments(q_lo), ens.moments(q_hi)))
+            if it + 1 < n_intervals:
+                _inject_all(ens, T[-1])
+            if progress:
+                torch.cuda.synchronize()
+                progress("runs %d-%d: interval %d of %d" % (c0, min(n_runs, c0 + chunk) - 1, it + 1, n_intervals))
+        del ens
+    return torch.cat(X), torch.cat(T)
+
+
+def evaluate_inloop(corr, n_inst, nz, interval, n_intervals, seed, tau_range=(0.01, 1.0), q_lo=8, q_hi=128,
+                    dtype="f32", tune=True, progress=None):
+    """Relative T^{mu nu} errors at t_end = n_intervals * interval of the plain
+    low-order solve and of the low-order solve with the correction injected
+    after every interval, against the high-order solve; wall times of the
+    corrected low-order path and of the high-order solve.  If the guard rejects
+    the features at some interval, the corrected path falls back to the
+    high-order solve (its time included)."""
+    rng = np.random.default_rng(seed)
+    states = _states(rng, n_inst, *tau_range)
+    ens = PairedEnsemble(states, nz, q_lo, q_hi, dtype)
+    plain = PairedEnsemble(states, nz, q_lo, q_lo, dtype)        # a second low-order copy, never corrected
+    k = int(round(interval / ens.dt))
+    stream = torch.cuda.current_stream()
+    if tune:
+        for Q in (q_lo, q_hi):
+            ens.batches[Q].autotune(reps=2, stream=stream)
+        plain.batches[q_lo].autotune(reps=2, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fallback = False
+    for it in range(n_intervals):
+        ens.advance(k, which=q_lo, stream=stream)
+        X = corr.features(ens)
+        if rsl.guard(X, corr.lo, corr.hi):
+            fallback = True
+            break
+        _inject_all(ens, corr.net.forward(X), stream=stream)
+    m_lo = ens.moments(q_lo)
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    if progress:
+        progress("in-loop corrected low-order solve: %.2f s" % t_learned)
+    t0 = time.perf_counter()
+    ens.advance(k * n_intervals, which=q_hi, stream=stream)
+    m_hi = ens.moments(q_hi)
+    torch.cuda.synchronize()
+    t_hi = time.perf_counter() - t0
+    plain.advance(k * n_intervals, which=q_lo, stream=stream)
+    m_plain = plain.moments(q_lo)
+    Thi = m_hi[:, 2:5]
+
+    def rel(a):
+        return float(torch.linalg.norm(a - Thi) / torch.linalg.norm(Thi))
+    if fallback:
+        t_learned += t_hi
+    return {"err_lo": rel(m_plain[:, 2:5]), "err_inloop": None if fallback else rel(m_lo[:, 2:5]),
+            "t_learned_s": t_learned, "t_high_order_s": t_hi, "fallback": fallback, "cells": int(Thi.shape[0])}
