@@ -30,7 +30,7 @@ import warnings
 import numpy as np
 from scipy.optimize import fsolve
 
-from . import Sod, feq, landau
+from . import TAU_INF, Sod, feq, landau
 
 GAMMA = 1.0 - 1.0 / np.sqrt(2.0)
 
@@ -41,6 +41,15 @@ def _rows(vs):
     return xi, p, np.stack([np.ones_like(xi), xi, p, p * xi, p * xi * xi])
 
 
+def _rate(S, L, xi):
+    """gamma (1 - beta xi_j) / tau_AW of the frame L; zero for the
+    collisionless law (tau_AW -> infinity, where the Anderson-Witting term of
+    eq. AW vanishes)."""
+    if S.s.tau_mode == TAU_INF:
+        return np.zeros_like(xi)
+    return L["gamma"] * (1.0 - L["beta"] * xi) / S.relax_time(L["n"], L["T"])
+
+
 def relaxed(S, Fc, M, X, h):
     """G for one cell: F column Fc, its moments M (5,), guess X = (N^z, T^zz)."""
     vs = S.vs
@@ -48,8 +57,7 @@ def relaxed(S, Fc, M, X, h):
     L = landau(np.array([M[0], X[0], M[2], M[3], X[1]]))
     if L is None:
         return None
-    tau = S.relax_time(L["n"], L["T"])
-    c = L["gamma"] * (1.0 - L["beta"] * xi) / tau
+    c = _rate(S, L, xi)
     fe = feq(vs, L["n"], L["T"], L["beta"])
     return (Fc + h * c * fe) / (1.0 + h * c)
 
@@ -82,9 +90,7 @@ def collision(S, G):
     out = np.empty_like(G)
     for s in range(G.shape[1]):
         L = landau(M[:, s])
-        tau = S.relax_time(L["n"], L["T"])
-        c = L["gamma"] * (1.0 - L["beta"] * xi) / tau
-        out[:, s] = -c * (G[:, s] - feq(vs, L["n"], L["T"], L["beta"]))
+        out[:, s] = -_rate(S, L, xi) * (G[:, s] - feq(vs, L["n"], L["T"], L["beta"]))
     return out
 
 
@@ -94,7 +100,7 @@ class ImexSod:
     def __init__(self, vs, nz, **kw):
         self.S = Sod(vs, nz, **kw)
         adv = dict(kw)
-        adv["tau_mode"] = 2                       # collisionless: L is the advection alone
+        adv["tau_mode"] = TAU_INF                 # collisionless: L is the advection alone
         self.A = Sod(vs, nz, **adv)
         self.vs, self.nz = vs, nz
 

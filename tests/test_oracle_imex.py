@@ -2,7 +2,8 @@
 its defining equation and the moments the collision conserves, a uniform
 equilibrium kept, the near-inviscid tube at dt >> tau_AW against the exact
 Riemann plateau (Sec. IV B 2; the explicit RK3 diverges there), and second
-order in dt against a fine explicit RK3 reference."""
+order in dt against a fine explicit RK3 reference, and the collisionless law
+reducing the scheme to Heun's method on the advection."""
 import numpy as np
 import pytest
 
@@ -79,3 +80,20 @@ def test_imex_second_order_in_dt():
         errs.append(np.max(np.abs(f - ref)))
     p1, p2 = np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])
     assert 1.7 < p1 < 2.5 and 1.7 < p2 < 2.5, (errs, p1, p2)
+
+
+def test_collisionless_imex_is_heun_on_the_advection():
+    """tau_AW -> infinity: Q = 0, so F1 = f, F2 = f + dt A(f) and the step is
+    the SSP Heun method f + dt/2 (A(f) + A(f + dt A(f))) on the oracle's
+    collisionless L."""
+    nz = 40
+    vs = oracle.VelocitySet(2, 6, 2)
+    kw = dict(nL=1.0, TL=1.0, nR=0.4, TR=0.8, tau_mode=oracle.TAU_INF, bc=oracle.BC_EQ)
+    T = imex.ImexSod(vs, nz, **kw)
+    A = oracle.Sod(vs, nz, **kw)
+    f = T.init() * inputs.smooth_perturbation(vs.V, nz, seed=3, amp=0.2)
+    dt = 0.5 / nz
+    a1 = A.L(f)
+    want = f + 0.5 * dt * (a1 + A.L(f + dt * a1))
+    got = T.step(f, dt)
+    assert np.max(np.abs(got - want)) < 1e-14 * np.max(np.abs(want))
