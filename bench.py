@@ -35,6 +35,8 @@ Prints one JSON line.  Its "aux" object carries further measurements:
   learned_inloop (only on request) the correction fed back into the
            low-order populations every 0.05 (rsl_mlp_inject), trained on
            teacher-forced runs, judged against R-SLB(4;128);
+  imex     the near-inviscid tube (N_z = 4096, R-SLB(4;8), tau_r = 1e-7)
+           stepped implicit-explicit at dt = 0.5 dz = 1.2e3 tau_r to t = 0.4;
   vel3d    a velocity set with azimuthal nodes (Q_L = 3, Q_xi = 16, Q_phi = 8,
            N_Omega = 4: 384 nodes) over 2^20 cells of seeded states moving in
            any direction: the equilibrium written (rsl_feq3) and the moments
@@ -87,7 +89,7 @@ def parse(argv=None):
                     help="comma-separated stage-kernel variant per velocity class (-1: empty), and an eighth "
                          "for the whole batch as one class (-1: per class); skips the autotuner")
     ap.add_argument("--aux", default="all",
-                    choices=("none", "all", "sweep", "c1", "bjorken", "scaled", "learned", "learned_c5", "vel3d",
+                    choices=("none", "all", "sweep", "c1", "bjorken", "scaled", "learned", "learned_c5", "vel3d", "imex",
                              "learned_inloop"),
                     help="also measure the aux legs (all: every one but learned_c5 and learned_inloop), or one of them")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -385,6 +387,61 @@ def c1_leg(torch, rsl, stream, cpu=True):
     return out
 
 
+def imex_leg(torch, rsl, stream, nz=4096, cpu=True):
+    """The stiff tube stepped implicit-explicit (rsl_step_imex): N_z = 4096,
+    R-SLB(4;8), Q_L = 3, tau_r = 1e-7, the paper's Sod states, equilibrium
+    ghosts, dt = 0.5 dz (dt / tau = 1.2e3) to t = 0.4: updates/s (cell-velocity
+    pairs per step) over the whole run, beside the step the explicit scheme's
+    stiffness guard would allow.  Parity: one more step on sampled cells
+    against the oracle's step of a 41-cell window around each; the plateau
+    against the exact Riemann solution."""
+    import numpy as np
+    import oracle
+    from oracle import imex, riemann
+    quad = rsl.Quadrature(QL, 8, 4)
+    prob = rsl.make_problem(nz=nz, bc="eq", tau_r=1e-7, nL=1.0, TL=1.0, nR=0.125, TR=0.5)
+    inst = rsl.Instance(quad, prob)
+    dt = 0.5 / nz
+    steps = int(round(0.4 / dt))
+    inst.init(stream=stream)
+    inst.step_imex(dt, 10, stream=stream)
+    inst.init(stream=stream)
+    inst.t = 0.0
+    sec = _events(torch, stream, lambda: inst.step_imex(dt, steps, stream=stream))
+    M = inst.moments(stream=stream).cpu().numpy()
+    st = riemann.riemann_star(1.0, 1.0, 0.125, 0.0625)
+    z = -0.5 + (np.arange(nz) + 0.5) / nz
+    t = inst.t
+    pl = (z > st["beta_C"] * t + 0.01) & (z < st["beta_shock"] * t - 0.01)
+    f = inst.f().cpu().numpy()
+    inst.step_imex(dt, 1, stream=stream)
+    g = inst.f().cpu().numpy()
+    vs = oracle.VelocitySet(QL, 8, 4)
+    err = 0.0
+    for c in np.random.default_rng(5).choice(np.arange(20, nz - 20), 8, replace=False):
+        W = imex.ImexSod(vs, 41, zlo=0.0, zhi=41.0 / nz, nL=1.0, TL=1.0, nR=0.125, TR=0.5,
+                         tau_mode=oracle.TAU_CONST, tau_r=1e-7, bc=oracle.BC_OUTFLOW)
+        want = W.step(f[:, c - 20:c + 21], dt)[:, 20]
+        err = max(err, float(np.max(np.abs(g[:, c] - want)) / np.max(np.abs(want))))
+    updates = float(nz) * quad.V * steps
+    out = {"workload": "Sod near-inviscid, implicit-explicit: N_z = 4096, Q_L = 3, Q_xi = 8, N_Omega = 4, "
+                       "tau_r = 1e-7, dt = 0.5 dz to t = 0.4 (%d steps), equilibrium ghosts, f64" % steps,
+           "value": updates / sec, "unit": "updates/s", "seconds": sec, "us_per_step": sec / steps * 1e6,
+           "dt_over_tau": dt / 1e-7, "explicit_dt_bound": rsl.max_dt(quad, prob)[1],
+           "sampled_step_rel_err_vs_oracle": err,
+           "plateau_P_rel_err": float(np.mean(M[pl, 7]) / st["PC"] - 1.0),
+           "plateau_beta_rel_err": float(np.mean(M[pl, 9]) / st["beta_C"] - 1.0),
+           "status": inst.status(stream=stream)}
+    if cpu:
+        T = imex.ImexSod(vs, nz, nL=1.0, TL=1.0, nR=0.125, TR=0.5, tau_mode=oracle.TAU_CONST, tau_r=1e-7,
+                         bc=oracle.BC_EQ)
+        f0 = T.init()
+        out["cpu_baseline"] = _oracle_rate(lambda: T.run(f0, dt, 3), 3.0 * nz * quad.V,
+                                           "3 oracle IMEX steps of the whole tube from the initial state "
+                                           "(numpy + scipy fsolve per cell, one core)")
+    return out
+
+
 def scaled_leg(torch, rsl, stream, copies=128, dev_steps=1000, steps=20, chunk=10):
     """The sweep scaled out of the last-level cache: 128 copies of each of its
     16 instances (2048 instances, 24.8 GB in the three f fields, FP64), run
@@ -645,6 +702,7 @@ def main():
                 "scaled": lambda: scaled_leg(torch, rsl, stream),
                 "learned": lambda: learned_leg(torch, stream),
                 "vel3d": lambda: vel3d_leg(torch, rsl, stream, cpu=cpu),
+                "imex": lambda: imex_leg(torch, rsl, stream, cpu=cpu),
                 "learned_inloop": lambda: learned_inloop_leg(torch, stream),
                 "learned_c5": lambda: learned_leg(torch, stream, n_runs=512, nz_train=8192, n_inst=512,
                                                   nz_eval=8192, epochs=100, chunk=128)}

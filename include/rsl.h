@@ -161,6 +161,24 @@ int rsl_init(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_de
 int rsl_step(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_dev,
              double* t, double dt, int nsteps, void* hip_stream);
 
+/* Advance a Sod instance by nsteps implicit-explicit steps, for time steps
+ * not bound by the relaxation time (Sec. I names the option; Sec. III F):
+ * the WENO5 advection explicit and the Anderson-Witting term implicit in the
+ * IMEX-SSP2(2,2,2) scheme (second order, L-stable implicit part;
+ * g = 1 - 1/sqrt(2)):
+ *   F1 = f + g dt Q(F1),  F2 = f + dt A(F1) + (1 - 2g) dt Q(F1) + g dt Q(F2),
+ *   f' = f + dt/2 (A(F1) + A(F2)) + dt/2 (Q(F1) + Q(F2)).
+ * Each implicit stage is solved per cell: the collision keeps N^0, T^00,
+ * T^0z, and Newton's method finds the N^z, T^zz whose Landau frame, tau and
+ * f^eq reproduce them.  Uses the work buffer of rsl_sizes after rsl_init
+ * (the two stage slots, the ghost states, the status word).  Only the CFL
+ * bound applies (RSL_EUNSTABLE if dt max|xi| / dz >= 1); no stiffness guard.
+ * A cell whose stage has no Landau frame or does not converge gets NaN and
+ * sets the status word (rsl_status).  Errors: RSL_EINVAL, RSL_EUNSUPPORTED
+ * (Bjorken, binary32 storage), RSL_EUNSTABLE. */
+int rsl_step_imex(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_dev, double* t, double dt,
+                  int nsteps, void* hip_stream);
+
 /* Per-cell fields written to out_dev on the stream, cell-major:
  * out[s*fields + field], in the order listed at RSL_NMOM.  fields is
  * RSL_MOM_RAW5 (the five moments of eq. macro_jk) or RSL_MOM_ALL (those and the

@@ -385,6 +385,25 @@ int rsl_step(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_de
     return RSL_OK;
 }
 
+int rsl_step_imex(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_dev, double* t, double dt,
+                  int nsteps, void* hip_stream) {
+    int rc = check_quad(q);
+    if (rc || (rc = check_problem(q, p))) return rc;
+    if (p->problem != RSL_SOD) return set_error(RSL_EUNSUPPORTED, "IMEX steps are built for the Sod problem");
+    if (p->dtype != RSL_F64) return set_error(RSL_EUNSUPPORTED, "IMEX steps are built for binary64 storage");
+    if (!f_dev || !work_dev || !t) return set_error(RSL_EINVAL, "null argument");
+    if (nsteps < 0) return set_error(RSL_EINVAL, "nsteps < 0");
+    if (!pos(dt)) return set_error(RSL_EINVAL, "dt must be > 0");
+    double xmax = 0.0;
+    for (double x : q->xi) xmax = std::max(xmax, std::fabs(x));
+    const double dz = (p->z_hi - p->z_lo) / p->nz;
+    if (dt * xmax / dz >= 1.0) return set_error(RSL_EUNSTABLE, "dt max|xi| / dz >= 1 (CFL)");
+    InstDesc d = make_desc(q, p, f_dev, work_dev, dt);
+    if (nsteps > 0 && (rc = launch_imex_steps(d, nsteps, (hipStream_t)hip_stream))) return rc;
+    *t += nsteps * dt;
+    return RSL_OK;
+}
+
 int rsl_moments(const rsl_quad* q, const rsl_problem* p, const void* f_dev, void* work_dev, double* out_dev,
                 int fields, void* hip_stream) {
     int rc = check_quad(q);

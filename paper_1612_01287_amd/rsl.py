@@ -71,6 +71,8 @@ _sig("rsl_init", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _vp])
 _sig("rsl_step", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _dp, ctypes.c_double,
                                 ctypes.c_int, _vp])
 _sig("rsl_moments", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _vp, ctypes.c_int, _vp])
+_sig("rsl_step_imex", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp, _dp, ctypes.c_double,
+                                     ctypes.c_int, _vp])
 _sig("rsl_status", ctypes.c_int, [_vp, ctypes.POINTER(Problem), _vp, _vp])
 _sig("rsl_last_error", ctypes.c_char_p, [])
 
@@ -181,6 +183,14 @@ class Instance:
         t = ctypes.c_double(self.t)
         check(_lib.rsl_step(self.quad.handle, ctypes.byref(self.p), f, w, ctypes.byref(t), float(dt),
                             int(nsteps), _stream(stream)))
+        self.t = t.value
+
+    def step_imex(self, dt, nsteps=1, stream=None):
+        """rsl_step_imex: implicit-explicit steps (binary64 Sod instances)."""
+        f, w = self._ptrs()
+        t = ctypes.c_double(self.t)
+        check(_lib.rsl_step_imex(self.quad.handle, ctypes.byref(self.p), f, w, ctypes.byref(t), float(dt),
+                                 int(nsteps), _stream(stream)))
         self.t = t.value
 
     def f(self):

@@ -1,0 +1,146 @@
+"""GPU parity of the implicit-explicit step (rsl_step_imex) against the
+oracle's IMEX-SSP2(2,2,2) step (oracle/imex.py): WENO5 advection explicit,
+the Anderson-Witting term implicit, each implicit stage solved per cell.
+Sec. I (a time step not bound by tau_AW), Sec. III F, Sec. IV B 2.
+
+Bar: max |f_gpu - f_oracle| / max |f_oracle| <= 1e-12 (binary64 storage).
+Cases: several blocks with a ragged tail and a single short block, 4 to 64
+lanes per cell and two angular nodes per lane, both ghost rules, the three relaxation-time laws, an odd Q_xi (a node at
+xi = 0), moving off-equilibrium states, and dt / tau_AW from 0.06 to 4e4."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import imex, riemann
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+
+TAU = {"const": oracle.TAU_CONST, "etas": oracle.TAU_ETAS, "inf": oracle.TAU_INF}
+
+
+@pytest.fixture(scope="module")
+def rsl():
+    from paper_1612_01287_amd import rsl as mod
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return mod
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _pair(rsl, QL, Q, NOm, nz, bc, tau_mode, tau_r, tau_aw0, states):
+    quad = rsl.Quadrature(QL, Q, NOm)
+    p = rsl.make_problem(nz=nz, bc=bc, tau_mode=tau_mode, tau_r=tau_r, tau_aw0=tau_aw0, **states)
+    inst = rsl.Instance(quad, p)
+    vs = oracle.VelocitySet(QL, Q, NOm)
+    T = imex.ImexSod(vs, nz, tau_mode=TAU[tau_mode], tau_r=tau_r, tau_aw0=tau_aw0, lambda_ref=1.0,
+                     bc=oracle.BC_OUTFLOW if bc == "outflow" else oracle.BC_EQ, **states)
+    return quad, inst, vs, T
+
+
+CASES = [
+    # QL, Q, NOm, nz, bc, tau law, tau_r, tau_aw0, dt dz^-1, steps, start
+    (3, 8, 4, 150, "eq", "const", 1e-3, 0.0, 0.5, 4, "sod"),          # dt / tau = 3.3
+    (3, 8, 4, 130, "eq", "const", 1e-7, 0.0, 0.5, 4, "sod"),          # dt / tau = 3.8e4
+    (3, 8, 3, 5, "outflow", "const", 1e-2, 0.0, 0.5, 3, "sod"),       # one short block
+    (2, 9, 3, 203, "outflow", "etas", 0.0, 0.03, 0.4, 3, "moving"),   # xi = 0 node
+    (3, 16, 5, 64, "outflow", "const", 0.05, 0.0, 0.9, 3, "moving"),  # dt / tau = 0.28
+    (2, 6, 2, 70, "eq", "inf", 0.0, 0.0, 0.5, 3, "moving"),           # collisionless
+    (3, 20, 5, 97, "eq", "const", 1e-4, 0.0, 0.5, 3, "sod"),          # 32 lanes per cell
+    (2, 100, 4, 70, "outflow", "const", 0.01, 0.0, 0.5, 2, "moving"), # two nodes per lane
+]
+
+
+@pytest.mark.parametrize("QL,Q,NOm,nz,bc,law,tau_r,tau_aw0,cfl,steps,start", CASES)
+def test_imex_matches_oracle(rsl, QL, Q, NOm, nz, bc, law, tau_r, tau_aw0, cfl, steps, start):
+    states = inputs.SOD_PAPER if start == "sod" else inputs.SOD_C1
+    quad, inst, vs, T = _pair(rsl, QL, Q, NOm, nz, bc, law, tau_r, tau_aw0, states)
+    inst.init()                                   # ghost states and status word
+    f0 = T.init()
+    if start == "moving":
+        z = -0.5 + (np.arange(nz) + 0.5) / nz
+        beta = 0.4 * np.sin(2.0 * np.pi * z)
+        f0 = np.stack([oracle.feq(vs, 1.0 + 0.3 * np.cos(np.pi * z[s]), 0.9 + 0.2 * z[s] ** 2, beta[s])
+                       for s in range(nz)], axis=1)
+        f0 = f0 * inputs.smooth_perturbation(vs.V, nz, seed=nz, amp=0.2)
+    inst.set_f(f0)
+    dt = cfl / (nz * np.max(np.abs(vs.xi)))
+    f = f0
+    for k in range(steps):                        # each step against the oracle's step of the same state
+        inst.step_imex(dt, 1)
+        got = inst.f().cpu().numpy()
+        want = T.step(f, dt)
+        assert _rel(got, want) < 1e-12, k
+        f = got
+    assert inst.status() == 0
+    assert inst.t == pytest.approx(steps * dt, rel=1e-15)
+
+
+def test_imex_keeps_a_uniform_equilibrium(rsl):
+    st = dict(nL=0.7, TL=1.2, nR=0.7, TR=1.2)
+    quad, inst, vs, T = _pair(rsl, 3, 8, 4, 100, "outflow", "const", 1e-4, 0.0, st)
+    inst.init()
+    f0 = inst.f().cpu().numpy()
+    inst.step_imex(0.5 / 100, 5)
+    assert np.max(np.abs(inst.f().cpu().numpy() - f0)) < 1e-14 * np.max(np.abs(f0))
+
+
+def test_imex_near_inviscid_plateau_at_size(rsl):
+    """The stiff tube the benchmark times (N_z = 4096, R-SLB(4;8), Q_L = 3,
+    tau_r = 1e-7, dt = 0.5 dz: dt / tau = 1.2e3) to t = 0.4: the plateau
+    between contact and shock at the exact Riemann pressure and velocity
+    (Sec. IV B 2), the particle number kept (the waves have not reached the
+    ghosts), and sampled cells of one more step against the oracle's step of
+    the same state (the step of a cell needs only its 7-cell neighbourhood)."""
+    nz = 4096
+    quad, inst, vs, T = _pair(rsl, 3, 8, 4, nz, "eq", "const", 1e-7, 0.0, inputs.SOD_PAPER)
+    inst.init()
+    dt = 0.5 / nz
+    n0 = inst.moments().cpu().numpy()[:, 0].sum()
+    inst.step_imex(dt, int(round(0.4 / dt)))
+    assert inst.status() == 0
+    M = inst.moments().cpu().numpy()
+    assert np.all(np.isfinite(M))
+    assert abs(M[:, 0].sum() - n0) < 1e-11 * n0
+    st = riemann.riemann_star(1.0, 1.0, 0.125, 0.0625)
+    z = -0.5 + (np.arange(nz) + 0.5) / nz
+    t = inst.t
+    plateau = (z > st["beta_C"] * t + 0.01) & (z < st["beta_shock"] * t - 0.01)
+    assert plateau.sum() > 100
+    assert np.mean(M[plateau, 7]) == pytest.approx(st["PC"], rel=2e-3)
+    assert np.mean(M[plateau, 9]) == pytest.approx(st["beta_C"], rel=2e-3)
+    # sampled cells of one more step: the oracle steps a 20-cell window around each
+    f = inst.f().cpu().numpy()
+    inst.step_imex(dt, 1)
+    g = inst.f().cpu().numpy()
+    for c in inputs.rng(5).choice(np.arange(20, nz - 20), 12, replace=False):
+        W = imex.ImexSod(vs, 41, zlo=0.0, zhi=41.0 / nz, tau_mode=oracle.TAU_CONST, tau_r=1e-7,
+                         bc=oracle.BC_OUTFLOW, **inputs.SOD_PAPER)      # the tube's dz
+        want = W.step(f[:, c - 20:c + 21], dt)[:, 20]     # cell c, 20 cells from either window edge
+        assert _rel(g[:, c], want) < 1e-12, c
+
+
+def test_imex_argument_errors(rsl):
+    q = rsl.Quadrature(3, 8, 4)
+    inst32 = rsl.Instance(q, rsl.make_problem(nz=16, dtype="f32"))
+    with pytest.raises(rsl.RslError) as e:
+        inst32.step_imex(0.01, 1)
+    assert e.value.code == rsl.RSL_EUNSUPPORTED
+    bj = rsl.Instance(rsl.Quadrature(3, 20, 2), rsl.make_problem(kind="bjorken", tau_mode="const", tau_r=0.3))
+    with pytest.raises(rsl.RslError) as e:
+        bj.step_imex(0.01, 1)
+    assert e.value.code == rsl.RSL_EUNSUPPORTED
+    inst = rsl.Instance(q, rsl.make_problem(nz=16))
+    inst.init()
+    with pytest.raises(rsl.RslError) as e:                      # dt max|xi| / dz >= 1
+        inst.step_imex(1.1 / 16, 1)
+    assert e.value.code == rsl.RSL_EUNSTABLE
+    with pytest.raises(rsl.RslError) as e:
+        inst.step_imex(0.01, -1)
+    assert e.value.code == rsl.RSL_EINVAL
+    f0 = inst.f().cpu().numpy()
+    inst.step_imex(0.01, 0)
+    assert inst.t == 0.0 and np.array_equal(inst.f().cpu().numpy(), f0)
