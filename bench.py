@@ -424,6 +424,23 @@ def imex_leg(torch, rsl, stream, nz=4096, cpu=True):
         want = W.step(f[:, c - 20:c + 21], dt)[:, 20]
         err = max(err, float(np.max(np.abs(g[:, c] - want)) / np.max(np.abs(want))))
     updates = float(nz) * quad.V * steps
+    # C1 (N_z = 400, R-SLB(3;8), tau_r = 1e-3, dt = 1.25e-3 > tau_r) without
+    # the stiffness guard, against the explicit RK3 run of the same tube
+    q1 = rsl.Quadrature(QL, 8, 3)
+    p1 = rsl.make_problem(nz=400, tau_r=1e-3, nL=1.0, TL=1.0, nR=0.4, TR=0.8)
+    c1 = rsl.Instance(q1, p1)
+    c1.init(stream=stream)
+    c1.step_imex(1.25e-3, 10, stream=stream)
+    c1.init(stream=stream)
+    sec1 = _events(torch, stream, lambda: c1.step_imex(1.25e-3, 200, stream=stream))
+    ex = rsl.Instance(q1, p1)
+    ex.init(stream=stream)
+    ex.step(1.25e-3, 200, stream=stream)
+    Mi, Me = c1.moments(stream=stream).cpu().numpy(), ex.moments(stream=stream).cpu().numpy()
+    c1_out = {"us_per_step": sec1 / 200 * 1e6, "updates_per_s": 400.0 * q1.V * 200 / sec1,
+              "max_rel_diff_vs_rk3": {k: float(np.max(np.abs(Mi[:, c] - Me[:, c])) / np.max(np.abs(Me[:, c])))
+                                      for k, c in (("N0", 0), ("T00", 2), ("P", 7))},
+              "status": c1.status(stream=stream)}
     out = {"workload": "Sod near-inviscid, implicit-explicit: N_z = 4096, Q_L = 3, Q_xi = 8, N_Omega = 4, "
                        "tau_r = 1e-7, dt = 0.5 dz to t = 0.4 (%d steps), equilibrium ghosts, f64" % steps,
            "value": updates / sec, "unit": "updates/s", "seconds": sec, "us_per_step": sec / steps * 1e6,
@@ -431,7 +448,7 @@ def imex_leg(torch, rsl, stream, nz=4096, cpu=True):
            "sampled_step_rel_err_vs_oracle": err,
            "plateau_P_rel_err": float(np.mean(M[pl, 7]) / st["PC"] - 1.0),
            "plateau_beta_rel_err": float(np.mean(M[pl, 9]) / st["beta_C"] - 1.0),
-           "status": inst.status(stream=stream)}
+           "status": inst.status(stream=stream), "c1_tube": c1_out}
     if cpu:
         T = imex.ImexSod(vs, nz, nL=1.0, TL=1.0, nR=0.125, TR=0.5, tau_mode=oracle.TAU_CONST, tau_r=1e-7,
                          bc=oracle.BC_EQ)
