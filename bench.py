@@ -37,6 +37,8 @@ Prints one JSON line.  Its "aux" object carries further measurements:
            teacher-forced runs, judged against R-SLB(4;128);
   imex     the near-inviscid tube (N_z = 4096, R-SLB(4;8), tau_r = 1e-7)
            stepped implicit-explicit at dt = 0.5 dz = 1.2e3 tau_r to t = 0.4;
+  ensemble_imex the headline's 1024 instances stepped implicit-explicit at
+           dt = 0.5/N_z for every instance;
   vel3d    a velocity set with azimuthal nodes (Q_L = 3, Q_xi = 16, Q_phi = 8,
            N_Omega = 4: 384 nodes) over 2^20 cells of seeded states moving in
            any direction: the equilibrium written (rsl_feq3) and the moments
@@ -90,6 +92,7 @@ def parse(argv=None):
                          "for the whole batch as one class (-1: per class); skips the autotuner")
     ap.add_argument("--aux", default="all",
                     choices=("none", "all", "sweep", "c1", "bjorken", "scaled", "learned", "learned_c5", "vel3d", "imex",
+                             "ensemble_imex",
                              "learned_inloop"),
                     help="also measure the aux legs (all: every one but learned_c5 and learned_inloop), or one of them")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -119,14 +122,16 @@ def ensemble_params(n=ENS_N, seed=ENS_SEED):
     return out
 
 
-def ensemble_batch(rsl, params):
+def ensemble_batch(rsl, params, imex=False):
+    """The uneven ensemble as a batch; imex: every instance at dt = 0.5/N_z,
+    created for implicit-explicit steps (CFL bound only)."""
     quads = {Q: rsl.Quadrature(QL, Q, min(Q - 1, 4)) for Q in (8, 16, 32, 64)}
     qs, probs, dts = [], [], []
     for nz, Q, TR, tau, dt in params:
         qs.append(quads[Q])
         probs.append(rsl.make_problem(nz=nz, dtype="f32", bc="outflow", tau_r=tau, nL=1.0, TL=1.0,
-                                      nR=TR ** 3, TR=TR))
-        dts.append(dt)
+                                      nR=TR ** 3, TR=TR, imex=imex))
+        dts.append(0.5 / nz if imex else dt)
     return rsl.Batch(qs, probs, dts), qs, probs
 
 
@@ -459,6 +464,44 @@ def imex_leg(torch, rsl, stream, nz=4096, cpu=True):
     return out
 
 
+def ensemble_imex_leg(torch, rsl, stream, params, dev_steps=80, steps=20, cpu=True):
+    """The uneven ensemble stepped implicit-explicit at dt = 0.5/N_z for every
+    instance (the explicit stage's guard takes dt = tau_r/2 below that on 169
+    of them): updates/s over `steps` batch steps after `dev_steps`, instances whose status
+    reports an unphysical or non-finite cell, and sampled cells of one more
+    step against the oracle's step (binary32 storage) of a 41-cell window."""
+    import numpy as np
+    import oracle
+    from oracle import imex
+    B, quads, probs = ensemble_batch(rsl, params, imex=True)
+    B.init(stream=stream)
+    B.step_imex(dev_steps, stream=stream)
+    sec = _events(torch, stream, lambda: B.step_imex(steps, stream=stream))
+    bad = sum(1 for s in B.instance_status(stream=stream) if s != 0)
+    rng = np.random.default_rng(7)
+    picks = [int(i) for i in rng.choice(len(params), 4, replace=False)]
+    before = {i: B.f(i).double().cpu().numpy() for i in picks}
+    B.step_imex(1, stream=stream)
+    err = 0.0
+    for i in picks:
+        nz, Q, TR, tau, _ = params[i]
+        c = int(rng.integers(20, nz - 20))
+        vs = oracle.VelocitySet(QL, Q, min(Q - 1, 4))
+        W = imex.ImexSod(vs, 41, store_f32=True, zlo=0.0, zhi=41.0 / nz, nL=1.0, TL=1.0, nR=TR ** 3, TR=TR,
+                         tau_mode=oracle.TAU_CONST, tau_r=tau, bc=oracle.BC_OUTFLOW)
+        want = W.step(before[i][:, c - 20:c + 21], 0.5 / nz)[:, 20]
+        got = B.f(i).double().cpu().numpy()[:, c]
+        err = max(err, float(np.max(np.abs(got - want)) / np.max(np.abs(want))))
+    updates = float(sum(nz * quads[i].V for i, (nz, *_rest) in enumerate(params))) * steps
+    n_small_tau = sum(1 for nz, Q, TR, tau, dt in params if dt < 0.5 / nz)
+    out = {"workload": "the uneven ensemble (same 1024 instances, f32) at dt = 0.5/N_z for every instance, "
+                       "implicit-explicit (%d of them have tau_r/2 < 0.5/N_z)" % n_small_tau,
+           "value": updates / sec, "unit": "updates/s", "ms_per_step": sec / steps * 1e3,
+           "timed_from_step": dev_steps, "instances_with_unphysical_cells": bad, "sampled_step_rel_err_vs_oracle": err}
+    del B
+    return out
+
+
 def scaled_leg(torch, rsl, stream, copies=128, dev_steps=1000, steps=20, chunk=10):
     """The sweep scaled out of the last-level cache: 128 copies of each of its
     16 instances (2048 instances, 24.8 GB in the three f fields, FP64), run
@@ -720,6 +763,7 @@ def main():
                 "learned": lambda: learned_leg(torch, stream),
                 "vel3d": lambda: vel3d_leg(torch, rsl, stream, cpu=cpu),
                 "imex": lambda: imex_leg(torch, rsl, stream, cpu=cpu),
+                "ensemble_imex": lambda: ensemble_imex_leg(torch, rsl, stream, params, cpu=cpu),
                 "learned_inloop": lambda: learned_inloop_leg(torch, stream),
                 "learned_c5": lambda: learned_leg(torch, stream, n_runs=512, nz_train=8192, n_inst=512,
                                                   nz_eval=8192, epochs=100, chunk=128)}

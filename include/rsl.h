@@ -66,6 +66,9 @@ extern "C" {
                               Landau frame, tau, f^eq coefficients) stays binary64 */
 
 #define RSL_FLAG_FORCE_UNSTABLE 1  /* rsl_step: skip the stiffness guard          */
+#define RSL_FLAG_IMEX           2  /* rsl_batch_create: the instance is stepped   */
+                                   /* implicit-explicit (CFL bound only); the     */
+                                   /* batch then refuses the explicit steps       */
 #define RSL_QUAD_HOST_ONLY      1  /* rsl_make_quadrature: build host tables only  */
 
 /* Fields of rsl_moments output, per cell, in this order. */
@@ -169,13 +172,15 @@ int rsl_step(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_de
  *   F1 = f + g dt Q(F1),  F2 = f + dt A(F1) + (1 - 2g) dt Q(F1) + g dt Q(F2),
  *   f' = f + dt/2 (A(F1) + A(F2)) + dt/2 (Q(F1) + Q(F2)).
  * Each implicit stage is solved per cell: the collision keeps N^0, T^00,
- * T^0z, and Newton's method finds the N^z, T^zz whose Landau frame, tau and
- * f^eq reproduce them.  Uses the work buffer of rsl_sizes after rsl_init
+ * T^0z, and Broyden's method (from a finite-difference Jacobian) finds the
+ * N^z, T^zz whose Landau frame, tau and f^eq reproduce them.  Binary64 or
+ * binary32 storage (f and the stages stored in the instance's dtype, all
+ * arithmetic in binary64).  Uses the work buffer of rsl_sizes after rsl_init
  * (the two stage slots, the ghost states, the status word).  Only the CFL
  * bound applies (RSL_EUNSTABLE if dt max|xi| / dz >= 1); no stiffness guard.
  * A cell whose stage has no Landau frame or does not converge gets NaN and
  * sets the status word (rsl_status).  Errors: RSL_EINVAL, RSL_EUNSUPPORTED
- * (Bjorken, binary32 storage), RSL_EUNSTABLE. */
+ * (Bjorken), RSL_EUNSTABLE. */
 int rsl_step_imex(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_dev, double* t, double dt,
                   int nsteps, void* hip_stream);
 
@@ -234,6 +239,16 @@ int rsl_batch_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* 
  * graph holds kernel launches and event waits only.  Results are bitwise
  * those of rsl_batch_step. */
 int rsl_batch_graph_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream);
+/* nsteps implicit-explicit steps (as rsl_step_imex) of every instance of a Sod
+ * batch, each with its own dt: per step four launches over the batch (two
+ * implicit stages, each one launch per class of velocity-set size, and two
+ * explicit passes).  Instances created with RSL_FLAG_IMEX were checked
+ * against the CFL bound only; such a batch refuses rsl_batch_step,
+ * rsl_batch_graph_step, rsl_batch_stage and rsl_batch_autotune
+ * (RSL_EUNSTABLE).  Builds its work-item lists (device memory owned by the
+ * batch) on the first call.  Errors: RSL_EINVAL, RSL_EUNSUPPORTED (Bjorken),
+ * RSL_EUNSTABLE (CFL). */
+int rsl_batch_step_imex(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream);
 /* One RK3 stage (1, 2 or 3) of every Sod instance, without advancing the
  * host-side times: stage s reads f_n and the stage field s-1 and writes stage
  * field s (stage 3 writes f_{n+1} over f_n).  For custom drivers and timing. */

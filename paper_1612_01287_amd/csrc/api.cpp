@@ -6,6 +6,7 @@
 #include <new>
 #include <string>
 
+#include "imex.h"
 #include "rsl_impl.h"
 
 namespace rsl {
@@ -147,6 +148,14 @@ void stability_limits(const rsl_quad* q, const rsl_problem* p, double* cfl_dt, d
         rate = std::max(rate, speed / tau_of(r.nII, r.PC / r.nII));
     }
     *stiff_dt = rate > 0.0 ? kappa / rate : 0.0;    // a non-positive tau leaves no stable step
+}
+
+int check_cfl(const rsl_quad* q, const rsl_problem* p, double dt) {
+    if (!(dt > 0.0 && std::isfinite(dt))) return set_error(RSL_EINVAL, "dt must be > 0");
+    double cfl_dt, stiff_dt;
+    stability_limits(q, p, &cfl_dt, &stiff_dt);
+    if (!(dt < cfl_dt)) return set_error(RSL_EUNSTABLE, "CFL number dt*max|xi|/dz >= 1");
+    return RSL_OK;
 }
 
 int check_stability(const rsl_quad* q, const rsl_problem* p, double dt) {
@@ -390,16 +399,11 @@ int rsl_step_imex(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* wo
     int rc = check_quad(q);
     if (rc || (rc = check_problem(q, p))) return rc;
     if (p->problem != RSL_SOD) return set_error(RSL_EUNSUPPORTED, "IMEX steps are built for the Sod problem");
-    if (p->dtype != RSL_F64) return set_error(RSL_EUNSUPPORTED, "IMEX steps are built for binary64 storage");
     if (!f_dev || !work_dev || !t) return set_error(RSL_EINVAL, "null argument");
     if (nsteps < 0) return set_error(RSL_EINVAL, "nsteps < 0");
-    if (!pos(dt)) return set_error(RSL_EINVAL, "dt must be > 0");
-    double xmax = 0.0;
-    for (double x : q->xi) xmax = std::max(xmax, std::fabs(x));
-    const double dz = (p->z_hi - p->z_lo) / p->nz;
-    if (dt * xmax / dz >= 1.0) return set_error(RSL_EUNSTABLE, "dt max|xi| / dz >= 1 (CFL)");
+    if ((rc = check_cfl(q, p, dt))) return rc;
     InstDesc d = make_desc(q, p, f_dev, work_dev, dt);
-    if (nsteps > 0 && (rc = launch_imex_steps(d, nsteps, (hipStream_t)hip_stream))) return rc;
+    if (nsteps > 0 && (rc = launch_imex_steps(d, p->dtype, nsteps, (hipStream_t)hip_stream))) return rc;
     *t += nsteps * dt;
     return RSL_OK;
 }

@@ -14,6 +14,7 @@
 #include <functional>
 #include <vector>
 
+#include "imex.h"
 #include "rsl_impl.h"
 
 struct rsl_batch {
@@ -49,6 +50,12 @@ struct rsl_batch {
     int ql_first[5] = {}, ql_count[5] = {};   // groups of each Q_L (1..4)
     std::vector<int> group_sizes;             // live instances per group, launch order
     bool merged = false;                      // Sod: every instance in one class (launch.all)
+    // implicit-explicit steps: instances created with RSL_FLAG_IMEX (CFL bound
+    // only) make the batch refuse the explicit steps; item lists built at the
+    // first rsl_batch_step_imex
+    bool imex = false;
+    void* imex_mem = nullptr;
+    rsl::ImexItems imex_items{};
 };
 
 namespace rsl {
@@ -406,6 +413,50 @@ void batch_drop_graph(rsl_batch* b) {
 
 using namespace rsl;
 
+namespace {
+
+const char* const kImexOnly =
+    "the batch holds instances created with RSL_FLAG_IMEX (CFL bound only): step it with rsl_batch_step_imex";
+
+// Item lists of the implicit-explicit steps, uploaded once.
+int imex_items(rsl_batch* b) {
+    if (b->imex_mem) return RSL_OK;
+    std::vector<std::vector<int2>> cls(kImexClasses);
+    std::vector<int2> x;
+    for (int i = 0; i < b->n; ++i) {
+        const int Q = b->quads[i]->Q, nz = b->probs[i].nz;
+        const int c = imex_class(Q), per = imex_cells_per_item(Q);
+        for (int s0 = 0; s0 < nz; s0 += per) cls[c].push_back(make_int2(i, s0));
+        for (int s0 = 0; s0 < nz; s0 += 64) x.push_back(make_int2(i, s0));
+    }
+    size_t total = align_up(sizeof(int2) * x.size(), 256);
+    for (const auto& v : cls) total += align_up(sizeof(int2) * v.size(), 256);
+    void* mem = nullptr;
+    if (hipMalloc(&mem, total) != hipSuccess) return set_error(RSL_EINVAL, "hipMalloc(imex items) failed");
+    std::vector<char> host(total, 0);
+    size_t off = 0;
+    ImexItems it{};
+    for (int c = 0; c < kImexClasses; ++c) {
+        std::memcpy(host.data() + off, cls[c].data(), sizeof(int2) * cls[c].size());
+        it.items[c] = (const int2*)((char*)mem + off);
+        it.n[c] = (int)cls[c].size();
+        off += align_up(sizeof(int2) * cls[c].size(), 256);
+    }
+    std::memcpy(host.data() + off, x.data(), sizeof(int2) * x.size());
+    it.x = (const int2*)((char*)mem + off);
+    it.nx = (int)x.size();
+    const int rc = hip_check(hipMemcpy(mem, host.data(), total, hipMemcpyHostToDevice), "hipMemcpy(imex items)");
+    if (rc) {
+        (void)hipFree(mem);
+        return rc;
+    }
+    b->imex_mem = mem;
+    b->imex_items = it;
+    return RSL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int rsl_batch_create(const rsl_quad* const* quads, const rsl_problem* problems, const double* dt, int n,
@@ -428,7 +479,9 @@ int rsl_batch_create(const rsl_quad* const* quads, const rsl_problem* problems, 
         else {
             size_t fb = 0, wb = 0;
             rc = rsl_sizes(q, &p, &fb, &wb);
-            if (rc == RSL_OK && (rc = check_stability(q, &p, dt[i])))
+            const bool imex = p.problem == RSL_SOD && (p.flags & RSL_FLAG_IMEX);
+            b->imex = b->imex || imex;
+            if (rc == RSL_OK && (rc = imex ? check_cfl(q, &p, dt[i]) : check_stability(q, &p, dt[i])))
                 set_error(rc, "batch instance " + std::to_string(i) + ": " + rsl_last_error());
             if (rc == RSL_OK) {
                 b->quads.push_back(q);
@@ -473,6 +526,7 @@ void rsl_batch_free(rsl_batch* b) {
         }
     }
     if (b->dmem) (void)hipFree(b->dmem);
+    if (b->imex_mem) (void)hipFree(b->imex_mem);
     delete b;
 }
 
@@ -520,12 +574,14 @@ int rsl_batch_stage(rsl_batch* b, void* f_dev, void* work_dev, int stage, void* 
     if (!b || !f_dev || !work_dev) return set_error(RSL_EINVAL, "null argument");
     if (b->kind != RSL_SOD) return set_error(RSL_EINVAL, "single stages exist for Sod batches only");
     if (stage < 1 || stage > 3) return set_error(RSL_EINVAL, "stage must be 1, 2 or 3");
+    if (b->imex) return set_error(RSL_EUNSTABLE, kImexOnly);
     return batch_stage_all(b, stage, (char*)f_dev, (char*)work_dev, (hipStream_t)hip_stream, 0);
 }
 
 int rsl_batch_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream) {
     if (!b || !f_dev || !work_dev) return set_error(RSL_EINVAL, "null argument");
     if (nsteps < 0) return set_error(RSL_EINVAL, "nsteps < 0");
+    if (b->imex) return set_error(RSL_EUNSTABLE, kImexOnly);
     const int rc = batch_steps(b, (char*)f_dev, (char*)work_dev, nsteps, (hipStream_t)hip_stream);
     if (rc == RSL_OK)
         for (int i = 0; i < b->n; ++i) b->t[i] += nsteps * b->dt[i];
@@ -535,6 +591,7 @@ int rsl_batch_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* 
 int rsl_batch_graph_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream) {
     if (!b || !f_dev || !work_dev) return set_error(RSL_EINVAL, "null argument");
     if (nsteps <= 0) return set_error(RSL_EINVAL, "nsteps must be > 0");
+    if (b->imex) return set_error(RSL_EUNSTABLE, kImexOnly);
     hipStream_t s = (hipStream_t)hip_stream;
     if (!s) return set_error(RSL_EINVAL, "graph replay needs an explicit (non-default) stream");
     int rc = RSL_OK;
@@ -640,6 +697,7 @@ int rsl_batch_autotune(rsl_batch* b, void* f_dev, void* work_dev, int reps, void
     if (!b || !f_dev || !work_dev) return set_error(RSL_EINVAL, "null argument");
     if (b->kind != RSL_SOD) return set_error(RSL_EINVAL, "kernel variants exist for Sod batches only");
     if (reps <= 0) return set_error(RSL_EINVAL, "reps must be > 0");
+    if (b->imex) return set_error(RSL_EUNSTABLE, kImexOnly);
     hipStream_t s = (hipStream_t)hip_stream;
     char* f = (char*)f_dev;
     char* w = (char*)work_dev;
@@ -781,3 +839,20 @@ int rsl_batch_instance_status(rsl_batch* b, void* work_dev, void* hip_stream, in
 }
 
 }  // extern "C"
+
+int rsl_batch_step_imex(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream) {
+    if (!b || !f_dev || !work_dev) return set_error(RSL_EINVAL, "null argument");
+    if (b->kind != RSL_SOD) return set_error(RSL_EUNSUPPORTED, "IMEX steps are built for Sod batches");
+    if (nsteps < 0) return set_error(RSL_EINVAL, "nsteps < 0");
+    int rc;
+    for (int i = 0; i < b->n; ++i)
+        if ((rc = check_cfl(b->quads[i], &b->probs[i], b->dt[i])))
+            return set_error(rc, "batch instance " + std::to_string(i) + ": " + rsl_last_error());
+    if (nsteps == 0) return RSL_OK;
+    if ((rc = imex_items(b))) return rc;
+    rc = launch_imex_batch_steps(b->launch.all.descs, b->imex_items, b->dtype, (char*)f_dev, (char*)work_dev, nsteps,
+                                 (hipStream_t)hip_stream);
+    if (rc) return rc;
+    for (int i = 0; i < b->n; ++i) b->t[i] += nsteps * b->dt[i];
+    return RSL_OK;
+}

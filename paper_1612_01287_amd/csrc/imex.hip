@@ -19,12 +19,15 @@
 // which follow from g_j, h_j and fixed quadrature sums; L lanes share a
 // cell, each taking every L-th angular node.
 //
-// Fields (binary64): f the state, F1 in the work buffer's first stage slot,
-// F2* then F2 (in place) in the second.
+// Fields (binary64 or binary32 storage, arithmetic in binary64): f the state,
+// F1 in the work buffer's first stage slot, F2* then F2 (in place) in the
+// second.  One instance per call, or a Sod batch (work items of one instance
+// each, per lanes-per-cell class).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 
+#include "imex.h"
 #include "rsl_impl.h"
 #include "rsl_math.h"
 
@@ -32,7 +35,8 @@ namespace rsl {
 
 namespace {
 
-constexpr int kImexThreads = 64;
+constexpr int kImexThreads = 64;        // single-instance workgroups
+constexpr int kImexBatchThreads = 256;  // batch implicit-stage workgroups (one instance each)
 constexpr double kImexG = 0.29289321881345247560;   // 1 - 1/sqrt(2)
 
 struct Frame {
@@ -76,17 +80,23 @@ struct LaneNodes {
     double P[JM <= 2 ? JM : 1][kMaxNOm + 1];
 };
 
-template <int L, int JM>
-__device__ __forceinline__ void load_nodes(const InstDesc& d, const double* __restrict__ F, int s, int r, LaneNodes<JM>& n) {
+template <typename Tf, int L, int JM>
+__device__ __forceinline__ void load_nodes(const InstDesc& d, const Tf* __restrict__ F, int s, int r,
+                                           LaneNodes<JM>& n) {
 #pragma unroll
     for (int i = 0; i < JM; ++i) {
         const int j = r + i * L;
         n.x[i] = n.a[i] = n.b[i] = n.w0[i] = n.w1[i] = n.w2[i] = n.w3[i] = 0.0;
+        if constexpr (JM <= 2) {
+#pragma unroll
+            for (int m = 0; m <= kMaxNOm; ++m) n.P[i][m] = 0.0;   // a node past Q_xi must not carry NaN
+        }
         if (j >= d.Q) continue;
         n.x[i] = d.tab.xi[j];
         for (int k = 0; k < d.QL; ++k) {
             const int v = k * d.Q + j;
-            const double fv = F[(size_t)v * d.pitch + s], w = d.tab.wxw[v], p = d.tab.pk[k], l1 = d.tab.L1[k];
+            const double fv = (double)F[(size_t)v * d.pitch + s], w = d.tab.wxw[v], p = d.tab.pk[k];
+            const double l1 = d.tab.L1[k];
             n.a[i] += fv;
             n.b[i] = fma(p, fv, n.b[i]);
             n.w0[i] += w;
@@ -130,23 +140,29 @@ __device__ __forceinline__ void relaxed_moments(const InstDesc& d, const LaneNod
     out[1] = group_sum<L>(tzz);
 }
 
-// One cell per group of L lanes; the groups of a wave are independent and
-// every lane of a group takes the same branches (its sums are bitwise equal).
-template <int L, int JM>
-__global__ void __launch_bounds__(kImexThreads) imex_implicit_kernel(InstDesc d, const double* Fs, double* G,
-                                                                      double h) {
+// The K-series tables of the instance's velocity set into LDS (read by every
+// frame evaluation).
+constexpr int kSer = kSeriesTerms * 2 * (kMaxNOm + 1);
+
+__device__ __forceinline__ void stage_tables(const InstDesc& d, double* ser, double* thr) {
+    for (int i = threadIdx.x; i < kSer; i += blockDim.x) ser[i] = d.tab.ser[i];
+    for (int i = threadIdx.x; i < kSeriesTerms; i += blockDim.x) thr[i] = d.tab.thr[i];
+    __syncthreads();
+}
+
+// One cell per group of L lanes (cell s0 + threadIdx.x / L of a workgroup);
+// the groups of a wave are independent and every lane of a group takes the
+// same branches (its sums are bitwise equal).  In place (Fs == G) is safe: a
+// group reads its cell's column before it writes any of it.
+template <typename Tf, int L, int JM>
+__device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, Tf* G, double h, int s_first,
+                                               const double* ser, const double* thr) {
     const int r = threadIdx.x % L;
-    const int s0 = blockIdx.x * (kImexThreads / L) + threadIdx.x / L;
+    const int s0 = s_first + threadIdx.x / L;
     const bool live = s0 < d.nz;
     const int s = live ? s0 : d.nz - 1;           // dead groups repeat the last cell and store nothing
-    // the Maclaurin tables of K_{3,m}, K_{4,m} in LDS (read by every frame)
-    constexpr int kSer = kSeriesTerms * 2 * (kMaxNOm + 1);
-    __shared__ double ser[kSer], thr[kSeriesTerms];
-    for (int i = threadIdx.x; i < kSer; i += kImexThreads) ser[i] = d.tab.ser[i];
-    for (int i = threadIdx.x; i < kSeriesTerms; i += kImexThreads) thr[i] = d.tab.thr[i];
-    __syncthreads();
     LaneNodes<JM> nd;
-    load_nodes<L, JM>(d, Fs, s, r, nd);
+    load_nodes<Tf, L, JM>(d, Fs, s, r, nd);
     double M[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < JM; ++i) {
@@ -214,7 +230,7 @@ __global__ void __launch_bounds__(kImexThreads) imex_implicit_kernel(InstDesc d,
     if (!ok || !conv) {
         if (r == 0) atomicOr(d.status, 1u);
         for (int j = r; j < d.Q; j += L)
-            for (int k = 0; k < d.QL; ++k) G[(size_t)(k * d.Q + j) * d.pitch + s] = __builtin_nan("");
+            for (int k = 0; k < d.QL; ++k) G[(size_t)(k * d.Q + j) * d.pitch + s] = (Tf)__builtin_nan("");
         return;
     }
     for (int j = r; j < d.Q; j += L) {
@@ -231,22 +247,48 @@ __global__ void __launch_bounds__(kImexThreads) imex_implicit_kernel(InstDesc d,
         for (int k = 0; k < d.QL; ++k) {
             const int v = k * d.Q + j;
             const double fe = d.tab.wxw[v] * fma(d.tab.L1[k], hh, g);
-            const double fv = Fs[(size_t)v * d.pitch + s];
-            G[(size_t)v * d.pitch + s] = fma(hc, fe, fv) * den;
+            const double fv = (double)Fs[(size_t)v * d.pitch + s];
+            G[(size_t)v * d.pitch + s] = (Tf)(fma(hc, fe, fv) * den);
         }
     }
 }
 
+template <typename Tf, int L, int JM>
+__global__ void __launch_bounds__(kImexThreads) imex_implicit_kernel(InstDesc d, const Tf* Fs, Tf* G, double h) {
+    __shared__ double ser[kSer], thr[kSeriesTerms];
+    stage_tables(d, ser, thr);
+    implicit_cells<Tf, L, JM>(d, Fs, G, h, blockIdx.x * (kImexThreads / L), ser, thr);
+}
+
+// Batch form: item (instance, first cell); second = 0 solves F1 from f,
+// second = 1 solves F2 from F2* in place.
+template <typename Tf, int L, int JM>
+__global__ void __launch_bounds__(kImexBatchThreads) imex_implicit_batch_kernel(const InstDesc* __restrict__ descs,
+                                                                            const int2* __restrict__ items,
+                                                                            char* fbase, char* wbase, int second) {
+    const int2 it = items[blockIdx.x];
+    InstDesc d = descs[it.x];
+    rebase(d, fbase, wbase);
+    __shared__ double ser[kSer], thr[kSeriesTerms];
+    stage_tables(d, ser, thr);
+    const Tf* F = (const Tf*)(second ? d.f2 : d.f);
+    Tf* G = (Tf*)(second ? d.f2 : d.f1);
+    implicit_cells<Tf, L, JM>(d, F, G, kImexG * d.dt, it.y, ser, thr);
+}
+
 // Population of velocity v at cell c (ghosts per the instance's rule).
-__device__ __forceinline__ double at(const InstDesc& d, const double* F, int v, int c) {
-    if (c < 0) return d.bc == RSL_BC_EQ ? d.feqL[v] : F[(size_t)v * d.pitch];
-    if (c >= d.nz) return d.bc == RSL_BC_EQ ? d.feqR[v] : F[(size_t)v * d.pitch + d.nz - 1];
-    return F[(size_t)v * d.pitch + c];
+template <typename Tf>
+__device__ __forceinline__ double at(const InstDesc& d, const Tf* F, int v, int c) {
+    if (c < 0) return d.bc == RSL_BC_EQ ? d.feqL[v] : (double)F[(size_t)v * d.pitch];
+    if (c >= d.nz) return d.bc == RSL_BC_EQ ? d.feqR[v] : (double)F[(size_t)v * d.pitch + d.nz - 1];
+    return (double)F[(size_t)v * d.pitch + c];
 }
 
 // A(F) at cell s, velocity v: -(Phi_{s+1/2} - Phi_{s-1/2}) / dz with the WENO5
-// flux Phi = xi_j weno5(upwind stencil) (Sec. III F).
-__device__ double advection(const InstDesc& d, const double* F, int v, int s) {
+// flux Phi = xi_j weno5(upwind stencil) (Sec. III F), in binary64 for either
+// storage.
+template <typename Tf>
+__device__ double advection(const InstDesc& d, const Tf* F, int v, int s) {
     const double x = d.tab.xv[v];
     if (x == 0.0) return 0.0;
     double u[7];
@@ -264,61 +306,160 @@ __device__ double advection(const InstDesc& d, const double* F, int v, int s) {
 
 // mode 0: F2* = f + dt A(F1) + (1 - 2g)/g (F1 - f) into the second slot;
 // mode 1: f <- f + dt/2 (A(F1) + A(F2)) + (F1 - f)/(2g) + (F2 - F2*)/(2g),
-// F2* recomputed from f, F1 and A(F1).  One thread per (cell, velocity v =
-// blockIdx.y).
-__global__ void __launch_bounds__(kImexThreads) imex_explicit_kernel(InstDesc d, int mode) {
-    const int s = blockIdx.x * kImexThreads + threadIdx.x;
-    const int v = blockIdx.y;
-    if (s >= d.nz) return;
-    double* f = (double*)d.f;
-    const double* F1 = (const double*)d.f1;
-    double* F2 = (double*)d.f2;
+// F2* recomputed (unrounded) from f, F1 and A(F1).
+template <typename Tf>
+__device__ __forceinline__ void explicit_point(const InstDesc& d, int v, int s, int mode) {
+    Tf* f = (Tf*)d.f;
+    const Tf* F1 = (const Tf*)d.f1;
+    Tf* F2 = (Tf*)d.f2;
     const double dt = d.dt, g = kImexG;
     const size_t i = (size_t)v * d.pitch + s;
-    const double fn = f[i], f1 = F1[i];
+    const double fn = (double)f[i], f1 = (double)F1[i];
     const double a1 = advection(d, F1, v, s);
     const double fs2 = fn + dt * a1 + (1.0 - 2.0 * g) / g * (f1 - fn);
     if (mode == 0) {
-        F2[i] = fs2;
+        F2[i] = (Tf)fs2;
     } else {
-        const double a2 = advection(d, F2, v, s);
-        const double out = fn + 0.5 * dt * (a1 + a2) + (f1 - fn) / (2.0 * g) + (F2[i] - fs2) / (2.0 * g);
-        if (!isfinite(out)) atomicOr(d.status, 2u);
-        f[i] = out;
+        const double a2 = advection(d, (const Tf*)F2, v, s);
+        const double out = fn + 0.5 * dt * (a1 + a2) + (f1 - fn) / (2.0 * g) + ((double)F2[i] - fs2) / (2.0 * g);
+        const Tf o = (Tf)out;
+        if (!isfinite(o)) atomicOr(d.status, 2u);
+        f[i] = o;
     }
+}
+
+// One thread per (cell, velocity v = blockIdx.y).
+template <typename Tf>
+__global__ void __launch_bounds__(kImexThreads) imex_explicit_kernel(InstDesc d, int mode) {
+    const int s = blockIdx.x * kImexThreads + threadIdx.x;
+    if (s < d.nz) explicit_point<Tf>(d, blockIdx.y, s, mode);
+}
+
+// Batch form: item (instance, first of 64 cells); velocities v = blockIdx.y,
+// blockIdx.y + kImexVY, ...
+constexpr int kImexVY = 8;
+
+template <typename Tf>
+__global__ void __launch_bounds__(kImexThreads) imex_explicit_batch_kernel(const InstDesc* __restrict__ descs,
+                                                                            const int2* __restrict__ items,
+                                                                            char* fbase, char* wbase, int mode) {
+    const int2 it = items[blockIdx.x];
+    InstDesc d = descs[it.x];
+    rebase(d, fbase, wbase);
+    const int s = it.y + threadIdx.x;
+    if (s >= d.nz) return;
+    for (int v = blockIdx.y; v < d.V; v += kImexVY) explicit_point<Tf>(d, v, s, mode);
+}
+
+
+// Lanes per cell and angular nodes per lane of each class: enough lanes to
+// cover the angular nodes, at most a wave; past 64 nodes each lane takes up
+// to 16 (Q_xi <= 1024).
+constexpr int kImexL[kImexClasses] = {4, 8, 16, 32, 64, 64, 64, 64, 64};
+
+template <typename Tf, int C>
+struct ImexClass;
+#define RSL_IMEX_CLASS(C, L, JM)                                                                              \
+    template <typename Tf>                                                                                    \
+    struct ImexClass<Tf, C> {                                                                                 \
+        static void single(const InstDesc& d, const Tf* F, Tf* G, double h, hipStream_t s) {                 \
+            const int cells = kImexThreads / L;                                                               \
+            hipLaunchKernelGGL((imex_implicit_kernel<Tf, L, JM>), dim3((d.nz + cells - 1) / cells),           \
+                               dim3(kImexThreads), 0, s, d, F, G, h);                                         \
+        }                                                                                                     \
+        static void batch(const InstDesc* descs, const int2* items, int n, char* fb, char* wb, int second,    \
+                          hipStream_t s) {                                                                    \
+            hipLaunchKernelGGL((imex_implicit_batch_kernel<Tf, L, JM>), dim3(n), dim3(kImexBatchThreads), 0, s, \
+                               descs, items, fb, wb, second);                                                 \
+        }                                                                                                     \
+    };
+RSL_IMEX_CLASS(0, 4, 1)
+RSL_IMEX_CLASS(1, 8, 1)
+RSL_IMEX_CLASS(2, 16, 1)
+RSL_IMEX_CLASS(3, 32, 1)
+RSL_IMEX_CLASS(4, 64, 1)
+RSL_IMEX_CLASS(5, 64, 2)
+RSL_IMEX_CLASS(6, 64, 4)
+RSL_IMEX_CLASS(7, 64, 8)
+RSL_IMEX_CLASS(8, 64, 16)
+#undef RSL_IMEX_CLASS
+
+template <typename Tf>
+void implicit_single(int c, const InstDesc& d, const Tf* F, Tf* G, double h, hipStream_t s) {
+    switch (c) {
+        case 0: ImexClass<Tf, 0>::single(d, F, G, h, s); break;
+        case 1: ImexClass<Tf, 1>::single(d, F, G, h, s); break;
+        case 2: ImexClass<Tf, 2>::single(d, F, G, h, s); break;
+        case 3: ImexClass<Tf, 3>::single(d, F, G, h, s); break;
+        case 4: ImexClass<Tf, 4>::single(d, F, G, h, s); break;
+        case 5: ImexClass<Tf, 5>::single(d, F, G, h, s); break;
+        case 6: ImexClass<Tf, 6>::single(d, F, G, h, s); break;
+        case 7: ImexClass<Tf, 7>::single(d, F, G, h, s); break;
+        default: ImexClass<Tf, 8>::single(d, F, G, h, s); break;
+    }
+}
+
+template <typename Tf>
+void implicit_batch(int c, const InstDesc* descs, const int2* items, int n, char* fb, char* wb, int second,
+                    hipStream_t s) {
+    switch (c) {
+        case 0: ImexClass<Tf, 0>::batch(descs, items, n, fb, wb, second, s); break;
+        case 1: ImexClass<Tf, 1>::batch(descs, items, n, fb, wb, second, s); break;
+        case 2: ImexClass<Tf, 2>::batch(descs, items, n, fb, wb, second, s); break;
+        case 3: ImexClass<Tf, 3>::batch(descs, items, n, fb, wb, second, s); break;
+        case 4: ImexClass<Tf, 4>::batch(descs, items, n, fb, wb, second, s); break;
+        case 5: ImexClass<Tf, 5>::batch(descs, items, n, fb, wb, second, s); break;
+        case 6: ImexClass<Tf, 6>::batch(descs, items, n, fb, wb, second, s); break;
+        case 7: ImexClass<Tf, 7>::batch(descs, items, n, fb, wb, second, s); break;
+        default: ImexClass<Tf, 8>::batch(descs, items, n, fb, wb, second, s); break;
+    }
+}
+
+template <typename Tf>
+int imex_steps_t(const InstDesc& d, int nsteps, hipStream_t s) {
+    const dim3 gx((d.nz + kImexThreads - 1) / kImexThreads, d.V);
+    const double h = kImexG * d.dt;
+    const int c = imex_class(d.Q);
+    for (int it = 0; it < nsteps; ++it) {
+        implicit_single<Tf>(c, d, (const Tf*)d.f, (Tf*)d.f1, h, s);
+        hipLaunchKernelGGL(imex_explicit_kernel<Tf>, gx, dim3(kImexThreads), 0, s, d, 0);
+        implicit_single<Tf>(c, d, (const Tf*)d.f2, (Tf*)d.f2, h, s);
+        hipLaunchKernelGGL(imex_explicit_kernel<Tf>, gx, dim3(kImexThreads), 0, s, d, 1);
+    }
+    return hip_check(hipGetLastError(), "imex step launch");
+}
+
+template <typename Tf>
+int imex_batch_steps_t(const InstDesc* descs, const ImexItems& it, char* fb, char* wb, int nsteps, hipStream_t s) {
+    const dim3 gx(it.nx, kImexVY);
+    for (int step = 0; step < nsteps; ++step) {
+        for (int second = 0; second < 2; ++second) {
+            for (int c = 0; c < kImexClasses; ++c)
+                if (it.n[c]) implicit_batch<Tf>(c, descs, it.items[c], it.n[c], fb, wb, second, s);
+            if (it.nx) hipLaunchKernelGGL(imex_explicit_batch_kernel<Tf>, gx, dim3(kImexThreads), 0, s, descs, it.x,
+                                          fb, wb, second);
+        }
+    }
+    return hip_check(hipGetLastError(), "imex batch step launch");
 }
 
 }  // namespace
 
-template <int L, int JM>
-static void implicit_stage(const InstDesc& d, const double* F, double* G, double h, hipStream_t s) {
-    const int cells = kImexThreads / L;
-    hipLaunchKernelGGL((imex_implicit_kernel<L, JM>), dim3((d.nz + cells - 1) / cells), dim3(kImexThreads), 0, s,
-                       d, F, G, h);
+int imex_class(int Q) {
+    return Q <= 4 ? 0 : Q <= 8 ? 1 : Q <= 16 ? 2 : Q <= 32 ? 3 : Q <= 64 ? 4 : Q <= 128 ? 5 : Q <= 256 ? 6
+                                                                                            : Q <= 512 ? 7 : 8;
 }
 
-int launch_imex_steps(const InstDesc& d, int nsteps, hipStream_t s) {
-    const dim3 gx((d.nz + kImexThreads - 1) / kImexThreads, d.V);
-    const double h = kImexG * d.dt;
-    // lanes per cell: enough to cover the angular nodes, at most a wave;
-    // past 64 nodes each lane takes up to 16 (Q_xi <= 1024)
-    using Stage = void (*)(const InstDesc&, const double*, double*, double, hipStream_t);
-    const Stage stage = d.Q <= 4    ? implicit_stage<4, 1>
-                        : d.Q <= 8   ? implicit_stage<8, 1>
-                        : d.Q <= 16  ? implicit_stage<16, 1>
-                        : d.Q <= 32  ? implicit_stage<32, 1>
-                        : d.Q <= 64  ? implicit_stage<64, 1>
-                        : d.Q <= 128 ? implicit_stage<64, 2>
-                        : d.Q <= 256 ? implicit_stage<64, 4>
-                        : d.Q <= 512 ? implicit_stage<64, 8>
-                                     : implicit_stage<64, 16>;
-    for (int it = 0; it < nsteps; ++it) {
-        stage(d, (const double*)d.f, (double*)d.f1, h, s);
-        hipLaunchKernelGGL(imex_explicit_kernel, gx, dim3(kImexThreads), 0, s, d, 0);
-        stage(d, (const double*)d.f2, (double*)d.f2, h, s);
-        hipLaunchKernelGGL(imex_explicit_kernel, gx, dim3(kImexThreads), 0, s, d, 1);
-    }
-    return hip_check(hipGetLastError(), "imex step launch");
+int imex_cells_per_item(int Q) { return kImexBatchThreads / kImexL[imex_class(Q)]; }
+
+int launch_imex_steps(const InstDesc& d, int dtype, int nsteps, hipStream_t s) {
+    return dtype == RSL_F64 ? imex_steps_t<double>(d, nsteps, s) : imex_steps_t<float>(d, nsteps, s);
+}
+
+int launch_imex_batch_steps(const InstDesc* descs, const ImexItems& items, int dtype, char* fbase, char* wbase,
+                            int nsteps, hipStream_t s) {
+    return dtype == RSL_F64 ? imex_batch_steps_t<double>(descs, items, fbase, wbase, nsteps, s)
+                            : imex_batch_steps_t<float>(descs, items, fbase, wbase, nsteps, s);
 }
 
 }  // namespace rsl

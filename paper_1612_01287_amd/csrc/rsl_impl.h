@@ -209,9 +209,6 @@ int launch_bj_mfma(const InstDesc* descs, const int* groups, int ngroups, int QL
 int launch_bj_steps(const InstDesc& d, double tau0, double dtau, int nsteps, hipStream_t s);
 int launch_bj_moments(const InstDesc& d, const void* f, double* out, int nf, hipStream_t s);
 
-// IMEX steps of a Sod instance (imex.hip), binary64 storage.
-int launch_imex_steps(const InstDesc& d, int nsteps, hipStream_t s);
-
 int launch_feq3(const Quad3Dev& q, const double* state, int ncell, int dtype, void* f, int pitch, hipStream_t s);
 int launch_moments3(const Quad3Dev& q, const void* f, int dtype, int ncell, int pitch, double* out, hipStream_t s);
 

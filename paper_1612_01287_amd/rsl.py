@@ -140,7 +140,7 @@ def max_dt(quad, problem):
 
 def make_problem(kind="sod", nz=400, dtype="f64", bc="outflow", tau_mode="const", gas="ideal",
                  z_lo=-0.5, z_hi=0.5, nL=1.0, TL=1.0, nR=0.4, TR=0.8, tau_r=1e-3, tau_aw0=0.0,
-                 lambda_ref=1.0, kappa=0.0, force=False):
+                 lambda_ref=1.0, kappa=0.0, force=False, imex=False):
     p = Problem()
     p.problem = C["RSL_SOD"] if kind == "sod" else C["RSL_BJORKEN"]
     p.nz = nz if kind == "sod" else 1
@@ -148,7 +148,7 @@ def make_problem(kind="sod", nz=400, dtype="f64", bc="outflow", tau_mode="const"
     p.bc = C["RSL_BC_OUTFLOW"] if bc == "outflow" else C["RSL_BC_EQ"]
     p.tau_mode = {"const": C["RSL_TAU_CONST"], "etas": C["RSL_TAU_ETAS"], "inf": C["RSL_TAU_INF"]}[tau_mode]
     p.gas = C["RSL_GAS_IDEAL"] if gas == "ideal" else C["RSL_GAS_PARTON"]
-    p.flags = C["RSL_FLAG_FORCE_UNSTABLE"] if force else 0
+    p.flags = (C["RSL_FLAG_FORCE_UNSTABLE"] if force else 0) | (C["RSL_FLAG_IMEX"] if imex else 0)
     p.z_lo, p.z_hi = z_lo, z_hi
     p.n_L, p.T_L, p.n_R, p.T_R = nL, TL, nR, TR
     p.tau_r, p.tau_aw0, p.lambda_ref, p.kappa = tau_r, tau_aw0, lambda_ref, kappa
@@ -225,6 +225,7 @@ _sig("rsl_batch_offset", ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes
 _sig("rsl_batch_time", ctypes.c_int, [_vp, ctypes.c_int, _dp])
 _sig("rsl_batch_init", ctypes.c_int, [_vp, _vp, _vp, _vp])
 _sig("rsl_batch_step", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
+_sig("rsl_batch_step_imex", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_stage", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_graph_step", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp])
 _sig("rsl_batch_set_path", ctypes.c_int, [_vp, ctypes.c_int])
@@ -282,6 +283,11 @@ class Batch:
     def step(self, nsteps=1, stream=None):
         f, w = self._ptrs()
         check(_lib.rsl_batch_step(self._h, f, w, int(nsteps), _stream(stream)))
+
+    def step_imex(self, nsteps=1, stream=None):
+        """rsl_batch_step_imex: implicit-explicit steps of every Sod instance."""
+        f, w = self._ptrs()
+        check(_lib.rsl_batch_step_imex(self._h, f, w, int(nsteps), _stream(stream)))
 
     def graph_step(self, nsteps=1, stream=None):
         """nsteps steps replayed from a captured HIP graph (needs a non-default stream)."""

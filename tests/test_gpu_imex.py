@@ -125,10 +125,6 @@ def test_imex_near_inviscid_plateau_at_size(rsl):
 
 def test_imex_argument_errors(rsl):
     q = rsl.Quadrature(3, 8, 4)
-    inst32 = rsl.Instance(q, rsl.make_problem(nz=16, dtype="f32"))
-    with pytest.raises(rsl.RslError) as e:
-        inst32.step_imex(0.01, 1)
-    assert e.value.code == rsl.RSL_EUNSUPPORTED
     bj = rsl.Instance(rsl.Quadrature(3, 20, 2), rsl.make_problem(kind="bjorken", tau_mode="const", tau_r=0.3))
     with pytest.raises(rsl.RslError) as e:
         bj.step_imex(0.01, 1)
@@ -173,3 +169,95 @@ def test_imex_c1_tube_without_the_guard(rsl):
     Me = ex.moments().cpu().numpy()
     for c, tol in ((0, 0.01), (2, 0.01), (7, 0.0125)):
         assert np.max(np.abs(Mi[:, c] - Me[:, c])) < tol * np.max(np.abs(Me[:, c])), c
+
+
+@pytest.mark.parametrize("QL,Q,NOm,nz,bc,law,tau_r,cfl,start", [
+    (3, 8, 4, 150, "eq", "const", 1e-3, 0.5, "sod"),
+    (3, 16, 4, 203, "outflow", "const", 1e-6, 0.5, "moving"),
+    (2, 100, 4, 70, "outflow", "const", 0.01, 0.5, "moving"),
+])
+def test_imex_binary32_matches_oracle(rsl, QL, Q, NOm, nz, bc, law, tau_r, cfl, start):
+    """Binary32 storage: the oracle rounds f and the stored stages F1, F2*,
+    F2 to binary32 where the kernels store them; bar 1e-5 per step."""
+    states = inputs.SOD_PAPER if start == "sod" else inputs.SOD_C1
+    quad = rsl.Quadrature(QL, Q, NOm)
+    inst = rsl.Instance(quad, rsl.make_problem(nz=nz, dtype="f32", bc=bc, tau_mode=law, tau_r=tau_r, **states))
+    vs = oracle.VelocitySet(QL, Q, NOm)
+    T = imex.ImexSod(vs, nz, store_f32=True, tau_mode=TAU[law], tau_r=tau_r,
+                     bc=oracle.BC_OUTFLOW if bc == "outflow" else oracle.BC_EQ, **states)
+    inst.init()
+    f = T.init()
+    if start == "moving":
+        z = -0.5 + (np.arange(nz) + 0.5) / nz
+        f = np.stack([oracle.feq(vs, 1.0 + 0.3 * np.cos(np.pi * z[s]), 0.9 + 0.2 * z[s] ** 2,
+                                 0.4 * np.sin(2.0 * np.pi * z[s])) for s in range(nz)], axis=1)
+        f = (f * inputs.smooth_perturbation(vs.V, nz, seed=nz, amp=0.2)).astype(np.float32).astype(np.float64)
+        inst.set_f(f)
+    dt = cfl / (nz * np.max(np.abs(vs.xi)))
+    for k in range(3):
+        inst.step_imex(dt, 1)
+        got = inst.f().double().cpu().numpy()
+        assert _rel(got, T.step(f, dt)) < 1e-5, k
+        f = got
+    assert inst.status() == 0
+
+
+BATCH = [  # QL, Q, NOm, nz, bc, tau_r, dtype
+    (3, 8, 4, 150, "eq", 1e-7, "f64"),
+    (3, 16, 4, 70, "outflow", 1e-3, "f64"),
+    (2, 3, 2, 5, "outflow", 0.05, "f64"),
+    (3, 20, 5, 97, "eq", 1e-4, "f64"),
+    (2, 100, 4, 64, "outflow", 0.01, "f64"),
+    (3, 64, 4, 203, "outflow", 1e-5, "f64"),
+]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_batch_imex_matches_oracle(rsl, dtype, tol):
+    """An uneven batch (5 velocity-set classes, ragged tails, a 5-cell tube,
+    dt / tau up to 2e4) created with RSL_FLAG_IMEX at dt = 0.5 dz for every
+    instance: each instance after two batch steps against two oracle steps,
+    and against the single-instance call."""
+    quads, probs, dts, pairs = [], [], [], []
+    for QL, Q, NOm, nz, bc, tau_r, _ in BATCH:
+        q = rsl.Quadrature(QL, Q, NOm)
+        quads.append(q)
+        probs.append(rsl.make_problem(nz=nz, dtype=dtype, bc=bc, tau_r=tau_r, imex=True, **inputs.SOD_PAPER))
+        dts.append(0.5 / nz)
+        vs = oracle.VelocitySet(QL, Q, NOm)
+        pairs.append(imex.ImexSod(vs, nz, store_f32=(dtype == "f32"), tau_mode=oracle.TAU_CONST, tau_r=tau_r,
+                                  bc=oracle.BC_OUTFLOW if bc == "outflow" else oracle.BC_EQ, **inputs.SOD_PAPER))
+    B = rsl.Batch(quads, probs, dts)
+    B.init()
+    B.step_imex(2)
+    for i, T in enumerate(pairs):
+        got = B.f(i).double().cpu().numpy()
+        want = T.run(T.init(), dts[i], 2)
+        assert _rel(got, want) < tol, i
+        single = rsl.Instance(quads[i], probs[i])
+        single.init()
+        single.step_imex(dts[i], 2)
+        assert _rel(got, single.f().double().cpu().numpy()) < 1e-14, i
+    assert B.status()[0] == 0
+
+
+def test_batch_imex_refuses_explicit_steps_and_checks_cfl(rsl):
+    q = rsl.Quadrature(3, 8, 4)
+    p = rsl.make_problem(nz=64, tau_r=1e-6, imex=True)
+    B = rsl.Batch([q], [p], [0.5 / 64])
+    B.init()
+    for call in (lambda: B.step(1), lambda: B.stage(1)):
+        with pytest.raises(rsl.RslError) as e:
+            call()
+        assert e.value.code == rsl.RSL_EUNSTABLE
+    with pytest.raises(rsl.RslError) as e:                      # CFL still applies
+        rsl.Batch([q], [p], [1.1 / 64])
+    assert e.value.code == rsl.RSL_EUNSTABLE
+    with pytest.raises(rsl.RslError) as e:                      # without the flag the guard applies
+        rsl.Batch([q], [rsl.make_problem(nz=64, tau_r=1e-6)], [0.5 / 64])
+    assert e.value.code == rsl.RSL_EUNSTABLE
+    bj = rsl.Batch([rsl.Quadrature(3, 20, 2)], [rsl.make_problem(kind="bjorken", tau_mode="const", tau_r=0.3)],
+                   [1e-3])
+    with pytest.raises(rsl.RslError) as e:
+        bj.step_imex(1)
+    assert e.value.code == rsl.RSL_EUNSUPPORTED

@@ -97,3 +97,20 @@ def test_collisionless_imex_is_heun_on_the_advection():
     want = f + 0.5 * dt * (a1 + A.L(f + dt * a1))
     got = T.step(f, dt)
     assert np.max(np.abs(got - want)) < 1e-14 * np.max(np.abs(want))
+
+
+def test_binary32_storage_rounds_only_what_is_stored():
+    """store_f32: every stored value is a binary32 number, the step stays
+    within binary32 rounding of the binary64 step from the same (rounded)
+    state, and the unrounded mode is untouched by the option."""
+    nz = 30
+    vs = oracle.VelocitySet(3, 8, 4)
+    kw = dict(nL=1.0, TL=1.0, nR=0.4, TR=0.8, tau_mode=oracle.TAU_CONST, tau_r=1e-3, bc=oracle.BC_OUTFLOW)
+    T32 = imex.ImexSod(vs, nz, store_f32=True, **kw)
+    T64 = imex.ImexSod(vs, nz, **kw)
+    f = T32.init() * inputs.smooth_perturbation(vs.V, nz, seed=9, amp=0.1)
+    f = f.astype(np.float32).astype(np.float64)
+    g32, g64 = T32.step(f, 0.5 / nz), T64.step(f, 0.5 / nz)
+    assert np.array_equal(g32, g32.astype(np.float32).astype(np.float64))
+    assert 0.0 < np.max(np.abs(g32 - g64)) < 1e-6 * np.max(np.abs(g64))
+    assert np.array_equal(T64.init(), oracle.Sod(vs, nz, **kw).init())
