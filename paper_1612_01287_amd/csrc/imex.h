@@ -9,7 +9,7 @@
 namespace rsl {
 
 // Classes of velocity sets by the lanes each cell's implicit solve takes
-// (4, 8, 16, 32, 64 lanes; then 64 lanes with 2, 4, 8, 16 angular nodes each).
+// (Q_xi <= 4, 8, 16, 32, 64, 128, 256, 512, 1024).
 constexpr int kImexClasses = 9;
 int imex_class(int Q);
 int imex_cells_per_item(int Q);   // cells of one batch implicit-stage workgroup

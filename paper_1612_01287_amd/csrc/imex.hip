@@ -72,12 +72,11 @@ __device__ __forceinline__ double group_sum(double x) {
 // A lane's angular nodes j = r + i L (i < JM) with what an evaluation needs
 // of them that does not depend on the frame: xi_j, the radial sums a_j =
 // sum_k F_jk, b_j = sum_k p_k F_jk of the cell, the quadrature sums
-// w0..w3 = sum_k w_j w_k {1, L_1(pbar_k), p_k, p_k L_1(pbar_k)}, and (for
-// JM <= 2) P_m(xi_j).  Nodes past Q_xi carry zeros.
+// w0..w3 = sum_k w_j w_k {1, L_1(pbar_k), p_k, p_k L_1(pbar_k)}.  Nodes past
+// Q_xi carry zeros.
 template <int JM>
 struct LaneNodes {
     double x[JM], a[JM], b[JM], w0[JM], w1[JM], w2[JM], w3[JM];
-    double P[JM <= 2 ? JM : 1][kMaxNOm + 1];
 };
 
 template <typename Tf, int L, int JM>
@@ -87,10 +86,6 @@ __device__ __forceinline__ void load_nodes(const InstDesc& d, const Tf* __restri
     for (int i = 0; i < JM; ++i) {
         const int j = r + i * L;
         n.x[i] = n.a[i] = n.b[i] = n.w0[i] = n.w1[i] = n.w2[i] = n.w3[i] = 0.0;
-        if constexpr (JM <= 2) {
-#pragma unroll
-            for (int m = 0; m <= kMaxNOm; ++m) n.P[i][m] = 0.0;   // a node past Q_xi must not carry NaN
-        }
         if (j >= d.Q) continue;
         n.x[i] = d.tab.xi[j];
         for (int k = 0; k < d.QL; ++k) {
@@ -104,18 +99,14 @@ __device__ __forceinline__ void load_nodes(const InstDesc& d, const Tf* __restri
             n.w2[i] = fma(w, p, n.w2[i]);
             n.w3[i] = fma(w * p, l1, n.w3[i]);
         }
-        if constexpr (JM <= 2) {
-#pragma unroll
-            for (int m = 0; m <= kMaxNOm; ++m) n.P[i][m] = m <= d.NOm ? d.tab.Pm[(size_t)m * d.Q + j] : 0.0;
-        }
     }
 }
 
 // (N^z, T^zz) of the relaxed stage G = (F + h c f^eq) / (1 + h c) for the
 // frame fr, summed over the cell's group of L lanes.
 template <int L, int JM>
-__device__ __forceinline__ void relaxed_moments(const InstDesc& d, const LaneNodes<JM>& n, int r, const Frame& fr, double h,
-                                double (&out)[2]) {
+__device__ __forceinline__ void relaxed_moments(const InstDesc& d, const LaneNodes<JM>& n, const double* Pm, int r,
+                                                const Frame& fr, double h, double (&out)[2]) {
     double nzs = 0.0, tzz = 0.0;
 #pragma unroll
     for (int i = 0; i < JM; ++i) {
@@ -124,9 +115,7 @@ __device__ __forceinline__ void relaxed_moments(const InstDesc& d, const LaneNod
 #pragma unroll
         for (int m = 0; m <= kMaxNOm; ++m) {       // fixed bounds keep c0, c1 in registers
             if (m > d.NOm) break;
-            double P;
-            if constexpr (JM <= 2) P = n.P[i][m];
-            else P = d.tab.Pm[(size_t)m * d.Q + j];
+            const double P = Pm[m * d.Q + j];
             g = fma(P, fr.c0[m], g);
             hh = fma(P, fr.c1[m], hh);
         }
@@ -143,11 +132,23 @@ __device__ __forceinline__ void relaxed_moments(const InstDesc& d, const LaneNod
 // The K-series tables of the instance's velocity set into LDS (read by every
 // frame evaluation).
 constexpr int kSer = kSeriesTerms * 2 * (kMaxNOm + 1);
+constexpr int kPmLds = (kMaxNOm + 1) * 128;   // P_m(xi_j) staged for Q_xi <= 128
 
-__device__ __forceinline__ void stage_tables(const InstDesc& d, double* ser, double* thr) {
-    for (int i = threadIdx.x; i < kSer; i += blockDim.x) ser[i] = d.tab.ser[i];
-    for (int i = threadIdx.x; i < kSeriesTerms; i += blockDim.x) thr[i] = d.tab.thr[i];
+struct ImexLds {
+    double ser[kSer], thr[kSeriesTerms], Pm[kPmLds];
+};
+
+// The tables into LDS; returns the P_m(xi_j) rows to read (the LDS copy, or
+// the global table past 128 nodes).
+__device__ __forceinline__ const double* stage_tables(const InstDesc& d, ImexLds& t) {
+    for (int i = threadIdx.x; i < kSer; i += blockDim.x) t.ser[i] = d.tab.ser[i];
+    for (int i = threadIdx.x; i < kSeriesTerms; i += blockDim.x) t.thr[i] = d.tab.thr[i];
+    const int np = (d.NOm + 1) * d.Q;
+    const bool lds = np <= kPmLds;
+    if (lds)
+        for (int i = threadIdx.x; i < np; i += blockDim.x) t.Pm[i] = d.tab.Pm[i];
     __syncthreads();
+    return lds ? t.Pm : d.tab.Pm;
 }
 
 // One cell per group of L lanes (cell s0 + threadIdx.x / L of a workgroup);
@@ -156,7 +157,7 @@ __device__ __forceinline__ void stage_tables(const InstDesc& d, double* ser, dou
 // group reads its cell's column before it writes any of it.
 template <typename Tf, int L, int JM>
 __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, Tf* G, double h, int s_first,
-                                               const double* ser, const double* thr) {
+                                               const double* ser, const double* thr, const double* Pm) {
     const int r = threadIdx.x % L;
     const int s0 = s_first + threadIdx.x / L;
     const bool live = s0 < d.nz;
@@ -177,54 +178,60 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
     double X[2] = {M[1], M[4]};
     const double sc[2] = {fabs(M[0]), fabs(M[2])};   // scales of the two unknowns
     // Broyden's method: a finite-difference Jacobian of R(X) = (relaxed
-    // moments - X) at the start, rank-one updates after each step above
-    // 1e-10 of the scales; one more step once a step is at 1e-13 of them
+    // moments - X) from the first three evaluations (X, X + e0, X + e1), then
+    // steps with rank-one updates after each step above 1e-10 of the scales;
+    // one more step once a step is at 1e-13 of them.  One evaluation site
+    // (frame, K-series, relaxed moments) serves all phases.
+    const double e0 = 1e-7 * sc[0], e1 = 1e-7 * sc[1];
     Frame fr;
-    bool ok = frame_of(d, M[0], X[0], M[2], M[3], X[1], ser, thr, fr), conv = false;
-    double R[2] = {0.0, 0.0}, J[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    if (ok) {
-        double r0[2], rp[2], rq[2];
-        relaxed_moments<L, JM>(d, nd, r, fr, h, r0);
-        const double e0 = 1e-7 * sc[0], e1 = 1e-7 * sc[1];
-        ok = frame_of(d, M[0], X[0] + e0, M[2], M[3], X[1], ser, thr, fr);
-        if (ok) relaxed_moments<L, JM>(d, nd, r, fr, h, rp);
-        ok = ok && frame_of(d, M[0], X[0], M[2], M[3], X[1] + e1, ser, thr, fr);
-        if (ok) {
-            relaxed_moments<L, JM>(d, nd, r, fr, h, rq);
-            R[0] = r0[0] - X[0];
-            R[1] = r0[1] - X[1];
-            J[0][0] = (rp[0] - r0[0]) / e0 - 1.0;
-            J[1][0] = (rp[1] - r0[1]) / e0;
-            J[0][1] = (rq[0] - r0[0]) / e1;
-            J[1][1] = (rq[1] - r0[1]) / e1 - 1.0;
+    bool ok = true, conv = false, last = false;
+    double R[2] = {0.0, 0.0}, J[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, r0[2] = {0.0, 0.0}, st[2] = {0.0, 0.0};
+    for (int it = 0; it < 43 && ok && !conv; ++it) {
+        const int phase = it < 3 ? it : 3;
+        double xe0 = X[0], xe1 = X[1];
+        if (phase == 1) xe0 += e0;
+        if (phase == 2) xe1 += e1;
+        if (phase == 3) {
+            const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            if (!(fabs(det) > 0.0)) { ok = false; break; }
+            st[0] = -(J[1][1] * R[0] - J[0][1] * R[1]) / det;
+            st[1] = -(J[0][0] * R[1] - J[1][0] * R[0]) / det;
+            X[0] += st[0];
+            X[1] += st[1];
+            xe0 = X[0];
+            xe1 = X[1];
         }
-    }
-    bool last = false;
-    for (int it = 0; it < 40 && ok && !conv; ++it) {
-        const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        if (!(fabs(det) > 0.0)) { ok = false; break; }
-        const double s0 = -(J[1][1] * R[0] - J[0][1] * R[1]) / det;
-        const double s1 = -(J[0][0] * R[1] - J[1][0] * R[0]) / det;
-        X[0] += s0;
-        X[1] += s1;
-        if (!frame_of(d, M[0], X[0], M[2], M[3], X[1], ser, thr, fr)) { ok = false; break; }
-        if (last) { conv = true; break; }            // fr is the frame of the final X
-        last = fabs(s0) <= 1e-13 * sc[0] && fabs(s1) <= 1e-13 * sc[1];
+        if (!frame_of(d, M[0], xe0, M[2], M[3], xe1, ser, thr, fr)) { ok = false; break; }
+        if (phase == 3 && last) { conv = true; break; }      // fr is the frame of the final X
         double rn[2];
-        relaxed_moments<L, JM>(d, nd, r, fr, h, rn);
-        const double y0 = rn[0] - X[0] - R[0], y1 = rn[1] - X[1] - R[1];
-        R[0] = rn[0] - X[0];
-        R[1] = rn[1] - X[1];
-        // no update from steps near the rounding level of R (its differences
-        // are noise there): the last Jacobian is kept
-        if (fabs(s0) <= 1e-10 * sc[0] && fabs(s1) <= 1e-10 * sc[1]) continue;
-        const double ss = s0 * s0 + s1 * s1;
-        const double u0 = (y0 - (J[0][0] * s0 + J[0][1] * s1)) / ss;
-        const double u1 = (y1 - (J[1][0] * s0 + J[1][1] * s1)) / ss;
-        J[0][0] += u0 * s0;
-        J[0][1] += u0 * s1;
-        J[1][0] += u1 * s0;
-        J[1][1] += u1 * s1;
+        relaxed_moments<L, JM>(d, nd, Pm, r, fr, h, rn);
+        if (phase == 0) {
+            r0[0] = rn[0];
+            r0[1] = rn[1];
+            R[0] = rn[0] - X[0];
+            R[1] = rn[1] - X[1];
+        } else if (phase == 1) {
+            J[0][0] = (rn[0] - r0[0]) / e0 - 1.0;
+            J[1][0] = (rn[1] - r0[1]) / e0;
+        } else if (phase == 2) {
+            J[0][1] = (rn[0] - r0[0]) / e1;
+            J[1][1] = (rn[1] - r0[1]) / e1 - 1.0;
+        } else {
+            last = fabs(st[0]) <= 1e-13 * sc[0] && fabs(st[1]) <= 1e-13 * sc[1];
+            const double y0 = rn[0] - X[0] - R[0], y1 = rn[1] - X[1] - R[1];
+            R[0] = rn[0] - X[0];
+            R[1] = rn[1] - X[1];
+            // no update from steps near the rounding level of R (its
+            // differences are noise there): the last Jacobian is kept
+            if (fabs(st[0]) <= 1e-10 * sc[0] && fabs(st[1]) <= 1e-10 * sc[1]) continue;
+            const double ss = st[0] * st[0] + st[1] * st[1];
+            const double u0 = (y0 - (J[0][0] * st[0] + J[0][1] * st[1])) / ss;
+            const double u1 = (y1 - (J[1][0] * st[0] + J[1][1] * st[1])) / ss;
+            J[0][0] += u0 * st[0];
+            J[0][1] += u0 * st[1];
+            J[1][0] += u1 * st[0];
+            J[1][1] += u1 * st[1];
+        }
     }
     if (!live) return;
     if (!ok || !conv) {
@@ -238,7 +245,7 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
 #pragma unroll
         for (int m = 0; m <= kMaxNOm; ++m) {
             if (m > d.NOm) break;
-            const double P = d.tab.Pm[(size_t)m * d.Q + j];
+            const double P = Pm[m * d.Q + j];
             g = fma(P, fr.c0[m], g);
             hh = fma(P, fr.c1[m], hh);
         }
@@ -255,9 +262,9 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
 
 template <typename Tf, int L, int JM>
 __global__ void __launch_bounds__(kImexThreads) imex_implicit_kernel(InstDesc d, const Tf* Fs, Tf* G, double h) {
-    __shared__ double ser[kSer], thr[kSeriesTerms];
-    stage_tables(d, ser, thr);
-    implicit_cells<Tf, L, JM>(d, Fs, G, h, blockIdx.x * (kImexThreads / L), ser, thr);
+    __shared__ ImexLds t;
+    const double* Pm = stage_tables(d, t);
+    implicit_cells<Tf, L, JM>(d, Fs, G, h, blockIdx.x * (kImexThreads / L), t.ser, t.thr, Pm);
 }
 
 // Batch form: item (instance, first cell); second = 0 solves F1 from f,
@@ -269,11 +276,11 @@ __global__ void __launch_bounds__(kImexBatchThreads) imex_implicit_batch_kernel(
     const int2 it = items[blockIdx.x];
     InstDesc d = descs[it.x];
     rebase(d, fbase, wbase);
-    __shared__ double ser[kSer], thr[kSeriesTerms];
-    stage_tables(d, ser, thr);
+    __shared__ ImexLds t;
+    const double* Pm = stage_tables(d, t);
     const Tf* F = (const Tf*)(second ? d.f2 : d.f);
     Tf* G = (Tf*)(second ? d.f2 : d.f1);
-    implicit_cells<Tf, L, JM>(d, F, G, kImexG * d.dt, it.y, ser, thr);
+    implicit_cells<Tf, L, JM>(d, F, G, kImexG * d.dt, it.y, t.ser, t.thr, Pm);
 }
 
 // Population of velocity v at cell c (ghosts per the instance's rule).
@@ -304,25 +311,27 @@ __device__ double advection(const InstDesc& d, const Tf* F, int v, int s) {
     return -x * (fp - fm) * d.dz_inv;
 }
 
-// mode 0: F2* = f + dt A(F1) + (1 - 2g)/g (F1 - f) into the second slot;
-// mode 1: f <- f + dt/2 (A(F1) + A(F2)) + (F1 - f)/(2g) + (F2 - F2*)/(2g),
-// F2* recomputed (unrounded) from f, F1 and A(F1).
+// mode 0: F2* = f + dt A(F1) + (1 - 2g)/g (F1 - f) into the second slot, and
+//         Y = f + dt/2 A(F1) + (F1 - f)/(2g) - F2*/(2g) (F2* unrounded) over f
+//         (each thread reads f at its own element only);
+// mode 1: f <- Y + dt/2 A(F2) + F2/(2g), which is
+//         f + dt/2 (A(F1) + A(F2)) + (F1 - f)/(2g) + (F2 - F2*)/(2g).
 template <typename Tf>
 __device__ __forceinline__ void explicit_point(const InstDesc& d, int v, int s, int mode) {
     Tf* f = (Tf*)d.f;
-    const Tf* F1 = (const Tf*)d.f1;
     Tf* F2 = (Tf*)d.f2;
     const double dt = d.dt, g = kImexG;
     const size_t i = (size_t)v * d.pitch + s;
-    const double fn = (double)f[i], f1 = (double)F1[i];
-    const double a1 = advection(d, F1, v, s);
-    const double fs2 = fn + dt * a1 + (1.0 - 2.0 * g) / g * (f1 - fn);
     if (mode == 0) {
+        const Tf* F1 = (const Tf*)d.f1;
+        const double fn = (double)f[i], f1 = (double)F1[i];
+        const double a1 = advection(d, F1, v, s);
+        const double fs2 = fn + dt * a1 + (1.0 - 2.0 * g) / g * (f1 - fn);
         F2[i] = (Tf)fs2;
+        f[i] = (Tf)(fn + 0.5 * dt * a1 + (f1 - fn - fs2) / (2.0 * g));
     } else {
         const double a2 = advection(d, (const Tf*)F2, v, s);
-        const double out = fn + 0.5 * dt * (a1 + a2) + (f1 - fn) / (2.0 * g) + ((double)F2[i] - fs2) / (2.0 * g);
-        const Tf o = (Tf)out;
+        const Tf o = (Tf)((double)f[i] + 0.5 * dt * a2 + (double)F2[i] / (2.0 * g));
         if (!isfinite(o)) atomicOr(d.status, 2u);
         f[i] = o;
     }
@@ -352,14 +361,17 @@ __global__ void __launch_bounds__(kImexThreads) imex_explicit_batch_kernel(const
 }
 
 
-// Lanes per cell and angular nodes per lane of each class: enough lanes to
-// cover the angular nodes, at most a wave; past 64 nodes each lane takes up
-// to 16 (Q_xi <= 1024).
-constexpr int kImexL[kImexClasses] = {4, 8, 16, 32, 64, 64, 64, 64, 64};
+// Lanes per cell (L) and angular nodes per lane (JM) of each class.  A single
+// instance spreads a cell over enough lanes to cover its angular nodes (at
+// most a wave; past 64 nodes each lane takes up to 16), since its few cells
+// leave the GPU short of waves.  A batch fills the GPU, so there each lane
+// takes several nodes and a wave serves more cells: the frame of a cell,
+// which every lane of its group evaluates, is then formed for fewer waves.
+constexpr int kImexBatchL[kImexClasses] = {4, 8, 8, 8, 16, 16, 64, 64, 64};
 
 template <typename Tf, int C>
 struct ImexClass;
-#define RSL_IMEX_CLASS(C, L, JM)                                                                              \
+#define RSL_IMEX_CLASS(C, L, JM, LB, JMB)                                                                     \
     template <typename Tf>                                                                                    \
     struct ImexClass<Tf, C> {                                                                                 \
         static void single(const InstDesc& d, const Tf* F, Tf* G, double h, hipStream_t s) {                 \
@@ -369,19 +381,21 @@ struct ImexClass;
         }                                                                                                     \
         static void batch(const InstDesc* descs, const int2* items, int n, char* fb, char* wb, int second,    \
                           hipStream_t s) {                                                                    \
-            hipLaunchKernelGGL((imex_implicit_batch_kernel<Tf, L, JM>), dim3(n), dim3(kImexBatchThreads), 0, s, \
-                               descs, items, fb, wb, second);                                                 \
+            static_assert(LB == kImexBatchL[C], "batch lanes per cell");                                      \
+            hipLaunchKernelGGL((imex_implicit_batch_kernel<Tf, LB, JMB>), dim3(n), dim3(kImexBatchThreads), 0, \
+                               s, descs, items, fb, wb, second);                                              \
         }                                                                                                     \
     };
-RSL_IMEX_CLASS(0, 4, 1)
-RSL_IMEX_CLASS(1, 8, 1)
-RSL_IMEX_CLASS(2, 16, 1)
-RSL_IMEX_CLASS(3, 32, 1)
-RSL_IMEX_CLASS(4, 64, 1)
-RSL_IMEX_CLASS(5, 64, 2)
-RSL_IMEX_CLASS(6, 64, 4)
-RSL_IMEX_CLASS(7, 64, 8)
-RSL_IMEX_CLASS(8, 64, 16)
+//              class  single    batch      angular nodes
+RSL_IMEX_CLASS(0, 4, 1, 4, 1)     // Q_xi <= 4
+RSL_IMEX_CLASS(1, 8, 1, 8, 1)     // <= 8
+RSL_IMEX_CLASS(2, 16, 1, 8, 2)    // <= 16
+RSL_IMEX_CLASS(3, 32, 1, 8, 4)    // <= 32
+RSL_IMEX_CLASS(4, 64, 1, 16, 4)   // <= 64
+RSL_IMEX_CLASS(5, 64, 2, 16, 8)   // <= 128
+RSL_IMEX_CLASS(6, 64, 4, 64, 4)   // <= 256
+RSL_IMEX_CLASS(7, 64, 8, 64, 8)   // <= 512
+RSL_IMEX_CLASS(8, 64, 16, 64, 16) // <= 1024
 #undef RSL_IMEX_CLASS
 
 template <typename Tf>
@@ -450,7 +464,7 @@ int imex_class(int Q) {
                                                                                             : Q <= 512 ? 7 : 8;
 }
 
-int imex_cells_per_item(int Q) { return kImexBatchThreads / kImexL[imex_class(Q)]; }
+int imex_cells_per_item(int Q) { return kImexBatchThreads / kImexBatchL[imex_class(Q)]; }
 
 int launch_imex_steps(const InstDesc& d, int dtype, int nsteps, hipStream_t s) {
     return dtype == RSL_F64 ? imex_steps_t<double>(d, nsteps, s) : imex_steps_t<float>(d, nsteps, s);
