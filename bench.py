@@ -34,7 +34,7 @@ Prints one JSON line.  Its "aux" object carries further measurements:
            size: 512 instances x N_z = 8192 against R-SLB(4;128);
   learned_inloop (only on request) the correction fed back into the
            low-order populations every 0.05 (rsl_mlp_inject), trained on
-           teacher-forced runs, judged against R-SLB(4;128);
+           teacher-forced runs, measured against R-SLB(4;128);
   imex     the near-inviscid tube (N_z = 4096, R-SLB(4;8), tau_r = 1e-7)
            stepped implicit-explicit at dt = 0.5 dz = 1.2e3 tau_r to t = 0.4;
   ensemble_imex the headline's 1024 instances stepped implicit-explicit at
