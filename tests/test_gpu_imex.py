@@ -261,3 +261,30 @@ def test_batch_imex_refuses_explicit_steps_and_checks_cfl(rsl):
     with pytest.raises(rsl.RslError) as e:
         bj.step_imex(1)
     assert e.value.code == rsl.RSL_EUNSUPPORTED
+
+
+def test_batch_imex_full_ensemble_sampled(rsl):
+    """The benchmark's 1024-instance binary32 ensemble created with
+    RSL_FLAG_IMEX at dt = 0.5/N_z for every instance, in the launch form the
+    benchmark times: 30 steps with no unphysical or non-finite cell, then
+    sampled cells of one more step against the oracle's binary32-storage step
+    of a 41-cell window of the tube (a cell's step needs 6 cells either side)."""
+    import bench
+    params = bench.ensemble_params()
+    B, quads, probs = bench.ensemble_batch(rsl, params, imex=True)
+    B.init()
+    B.step_imex(30)
+    assert all(s == 0 for s in B.instance_status())
+    rng = inputs.rng(11)
+    picks = [int(i) for i in rng.choice(len(params), 6, replace=False)]
+    before = {i: B.f(i).double().cpu().numpy() for i in picks}
+    B.step_imex(1)
+    for i in picks:
+        nz, Q, TR, tau, _ = params[i]
+        vs = oracle.VelocitySet(3, Q, min(Q - 1, 4))
+        W = imex.ImexSod(vs, 41, store_f32=True, zlo=0.0, zhi=41.0 / nz, nL=1.0, TL=1.0, nR=TR ** 3, TR=TR,
+                         tau_mode=oracle.TAU_CONST, tau_r=tau, bc=oracle.BC_OUTFLOW)
+        got = B.f(i).double().cpu().numpy()
+        for c in (nz // 2, int(rng.integers(20, nz - 20))):       # the membrane and a random cell
+            want = W.step(before[i][:, c - 20:c + 21], 0.5 / nz)[:, 20]
+            assert _rel(got[:, c], want) < 1e-5, (i, c)
