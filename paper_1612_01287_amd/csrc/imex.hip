@@ -365,9 +365,11 @@ __global__ void __launch_bounds__(kImexThreads) imex_explicit_batch_kernel(const
 // instance spreads a cell over enough lanes to cover its angular nodes (at
 // most a wave; past 64 nodes each lane takes up to 16), since its few cells
 // leave the GPU short of waves.  A batch fills the GPU, so there each lane
-// takes several nodes and a wave serves more cells: the frame of a cell,
-// which every lane of its group evaluates, is then formed for fewer waves.
-constexpr int kImexBatchL[kImexClasses] = {4, 8, 8, 8, 16, 16, 64, 64, 64};
+// takes two nodes (up to 128 nodes) and a wave serves twice the cells: the
+// frame of a cell, which every lane of its group evaluates, is then formed
+// for half the waves.  More nodes per lane push the registers past two waves
+// per SIMD, which costs more than the saved frames (measured).
+constexpr int kImexBatchL[kImexClasses] = {4, 8, 8, 16, 32, 64, 64, 64, 64};
 
 template <typename Tf, int C>
 struct ImexClass;
@@ -390,9 +392,9 @@ struct ImexClass;
 RSL_IMEX_CLASS(0, 4, 1, 4, 1)     // Q_xi <= 4
 RSL_IMEX_CLASS(1, 8, 1, 8, 1)     // <= 8
 RSL_IMEX_CLASS(2, 16, 1, 8, 2)    // <= 16
-RSL_IMEX_CLASS(3, 32, 1, 8, 4)    // <= 32
-RSL_IMEX_CLASS(4, 64, 1, 16, 4)   // <= 64
-RSL_IMEX_CLASS(5, 64, 2, 16, 8)   // <= 128
+RSL_IMEX_CLASS(3, 32, 1, 16, 2)   // <= 32
+RSL_IMEX_CLASS(4, 64, 1, 32, 2)   // <= 64
+RSL_IMEX_CLASS(5, 64, 2, 64, 2)   // <= 128
 RSL_IMEX_CLASS(6, 64, 4, 64, 4)   // <= 256
 RSL_IMEX_CLASS(7, 64, 8, 64, 8)   // <= 512
 RSL_IMEX_CLASS(8, 64, 16, 64, 16) // <= 1024
