@@ -292,15 +292,16 @@ __device__ __forceinline__ double at(const InstDesc& d, const Tf* F, int v, int 
 }
 
 // A(F) at cell s, velocity v: -(Phi_{s+1/2} - Phi_{s-1/2}) / dz with the WENO5
-// flux Phi = xi_j weno5(upwind stencil) (Sec. III F), in binary64 for either
-// storage.
+// flux Phi = xi_j weno5(upwind stencil) (Sec. III F), the stencil in the
+// storage precision (binary32 storage: the binary32 weights of the explicit
+// stages, with their limiting cases), the difference in binary64.
 template <typename Tf>
 __device__ double advection(const InstDesc& d, const Tf* F, int v, int s) {
     const double x = d.tab.xv[v];
     if (x == 0.0) return 0.0;
-    double u[7];
-    for (int q = 0; q < 7; ++q) u[q] = at(d, F, v, s - 3 + q);
-    double fp, fm;
+    Tf u[7];
+    for (int q = 0; q < 7; ++q) u[q] = (Tf)at(d, F, v, s - 3 + q);
+    Tf fp, fm;
     if (x > 0.0) {
         fp = weno5(u[1], u[2], u[3], u[4], u[5]);
         fm = weno5(u[0], u[1], u[2], u[3], u[4]);
@@ -308,7 +309,7 @@ __device__ double advection(const InstDesc& d, const Tf* F, int v, int s) {
         fp = weno5(u[6], u[5], u[4], u[3], u[2]);
         fm = weno5(u[5], u[4], u[3], u[2], u[1]);
     }
-    return -x * (fp - fm) * d.dz_inv;
+    return -x * ((double)fp - (double)fm) * d.dz_inv;
 }
 
 // mode 0: F2* = f + dt A(F1) + (1 - 2g)/g (F1 - f) into the second slot, and
