@@ -174,8 +174,9 @@ int rsl_step(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_de
  * Each implicit stage is solved per cell: the collision keeps N^0, T^00,
  * T^0z, and Broyden's method (from a finite-difference Jacobian) finds the
  * N^z, T^zz whose Landau frame, tau and f^eq reproduce them.  Binary64 or
- * binary32 storage (f and the stages stored in the instance's dtype, all
- * arithmetic in binary64).  Uses the work buffer of rsl_sizes after rsl_init
+ * binary32 storage (f and the stages stored in the instance's dtype; the
+ * arithmetic in binary64 except the WENO5 stencil of binary32 storage, which
+ * takes binary32 weights as rsl_step does).  Uses the work buffer of rsl_sizes after rsl_init
  * (the two stage slots, the ghost states, the status word).  Only the CFL
  * bound applies (RSL_EUNSTABLE if dt max|xi| / dz >= 1); no stiffness guard.
  * A cell whose stage has no Landau frame or does not converge gets NaN and
