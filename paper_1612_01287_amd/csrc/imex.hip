@@ -268,9 +268,11 @@ __global__ void __launch_bounds__(kImexThreads) imex_implicit_kernel(InstDesc d,
 }
 
 // Batch form: item (instance, first cell); second = 0 solves F1 from f,
-// second = 1 solves F2 from F2* in place.
+// second = 1 solves F2 from F2* in place.  One node per lane fits three waves
+// per SIMD without spills (164 VGPRs); two nodes per lane stay at two (three
+// would spill, measured slower).
 template <typename Tf, int L, int JM>
-__global__ void __launch_bounds__(kImexBatchThreads) imex_implicit_batch_kernel(const InstDesc* __restrict__ descs,
+__global__ void __launch_bounds__(kImexBatchThreads, JM == 1 ? 3 : 1) imex_implicit_batch_kernel(const InstDesc* __restrict__ descs,
                                                                             const int2* __restrict__ items,
                                                                             char* fbase, char* wbase, int second) {
     const int2 it = items[blockIdx.x];
