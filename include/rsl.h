@@ -247,8 +247,9 @@ int rsl_batch_graph_step(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, 
  * against the CFL bound only; such a batch refuses rsl_batch_step,
  * rsl_batch_graph_step, rsl_batch_stage and rsl_batch_autotune
  * (RSL_EUNSTABLE).  Builds its work-item lists (device memory owned by the
- * batch) on the first call.  Errors: RSL_EINVAL, RSL_EUNSUPPORTED (Bjorken),
- * RSL_EUNSTABLE (CFL). */
+ * batch, freed by rsl_batch_free) on the first call with nsteps > 0, so make
+ * that call outside HIP graph capture; later calls allocate nothing.
+ * Errors: RSL_EINVAL, RSL_EUNSUPPORTED (Bjorken), RSL_EUNSTABLE (CFL). */
 int rsl_batch_step_imex(rsl_batch* b, void* f_dev, void* work_dev, int nsteps, void* hip_stream);
 /* One RK3 stage (1, 2 or 3) of every Sod instance, without advancing the
  * host-side times: stage s reads f_n and the stage field s-1 and writes stage
