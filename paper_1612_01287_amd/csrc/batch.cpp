@@ -427,7 +427,7 @@ int imex_items(rsl_batch* b) {
         const int Q = b->quads[i]->Q, nz = b->probs[i].nz;
         const int c = imex_class(Q), per = imex_cells_per_item(Q);
         for (int s0 = 0; s0 < nz; s0 += per) cls[c].push_back(make_int2(i, s0));
-        for (int s0 = 0; s0 < nz; s0 += 64) x.push_back(make_int2(i, s0));
+        for (int s0 = 0; s0 < nz; s0 += imex_cells_per_explicit_item()) x.push_back(make_int2(i, s0));
     }
     size_t total = align_up(sizeof(int2) * x.size(), 256);
     for (const auto& v : cls) total += align_up(sizeof(int2) * v.size(), 256);

@@ -13,10 +13,11 @@ namespace rsl {
 constexpr int kImexClasses = 9;
 int imex_class(int Q);
 int imex_cells_per_item(int Q);   // cells of one batch implicit-stage workgroup
+int imex_cells_per_explicit_item();   // cells of one batch explicit-pass workgroup
 
 // Device item lists of a batch: per class (instance, first cell) of each
-// implicit-stage workgroup, and (instance, first of 64 cells) of the explicit
-// passes.
+// implicit-stage workgroup, and (instance, first cell) of each explicit-pass
+// workgroup.
 struct ImexItems {
     const int2* items[kImexClasses];
     int n[kImexClasses];

@@ -293,62 +293,75 @@ __device__ __forceinline__ double at(const InstDesc& d, const Tf* F, int v, int 
     return (double)F[(size_t)v * d.pitch + c];
 }
 
-// A(F) at cell s, velocity v: -(Phi_{s+1/2} - Phi_{s-1/2}) / dz with the WENO5
-// flux Phi = xi_j weno5(upwind stencil) (Sec. III F), the stencil in the
-// storage precision (binary32 storage: the binary32 weights of the explicit
-// stages, with their limiting cases), the difference in binary64.
-template <typename Tf>
-__device__ double advection(const InstDesc& d, const Tf* F, int v, int s) {
-    const double x = d.tab.xv[v];
-    if (x == 0.0) return 0.0;
-    Tf u[7];
-    for (int q = 0; q < 7; ++q) u[q] = (Tf)at(d, F, v, s - 3 + q);
-    Tf fp, fm;
-    if (x > 0.0) {
-        fp = weno5(u[1], u[2], u[3], u[4], u[5]);
-        fm = weno5(u[0], u[1], u[2], u[3], u[4]);
-    } else {
-        fp = weno5(u[6], u[5], u[4], u[3], u[2]);
-        fm = weno5(u[5], u[4], u[3], u[2], u[1]);
-    }
-    return -x * ((double)fp - (double)fm) * d.dz_inv;
+// Explicit passes: each thread takes RUN consecutive cells of one velocity
+// plane, so that the run's RUN + 1 interface fluxes come from one window of
+// RUN + 6 values (each face's WENO5 once, shared by the two cells it bounds).
+// Batches take runs of kImexRun cells; a single instance, short of threads,
+// one cell per thread.
+constexpr int kImexRun = 4;
+
+// Interface fluxes Phi_{s0 + f - 1/2}, f = 0..RUN, of velocity v (without
+// the factor xi_j), from the WENO5 upwind stencil (Sec. III F) in the storage
+// precision (binary32 storage: the binary32 weights of the explicit stages,
+// with their limiting cases).
+template <typename Tf, int RUN>
+__device__ __forceinline__ void run_fluxes(const InstDesc& d, const Tf* F, int v, int s0, double x,
+                                           Tf (&ph)[RUN + 1]) {
+    Tf u[RUN + 6];
+#pragma unroll
+    for (int q = 0; q < RUN + 6; ++q) u[q] = (Tf)at(d, F, v, s0 - 3 + q);
+#pragma unroll
+    for (int f = 0; f <= RUN; ++f)
+        ph[f] = x > 0.0 ? weno5(u[f], u[f + 1], u[f + 2], u[f + 3], u[f + 4])
+                        : weno5(u[f + 5], u[f + 4], u[f + 3], u[f + 2], u[f + 1]);
 }
 
 // mode 0: F2* = f + dt A(F1) + (1 - 2g)/g (F1 - f) into the second slot, and
 //         Y = f + dt/2 A(F1) + (F1 - f)/(2g) - F2*/(2g) (F2* unrounded) over f
-//         (each thread reads f at its own element only);
+//         (each thread reads f at its own elements only);
 // mode 1: f <- Y + dt/2 A(F2) + F2/(2g), which is
-//         f + dt/2 (A(F1) + A(F2)) + (F1 - f)/(2g) + (F2 - F2*)/(2g).
-template <typename Tf>
-__device__ __forceinline__ void explicit_point(const InstDesc& d, int v, int s, int mode) {
+//         f + dt/2 (A(F1) + A(F2)) + (F1 - f)/(2g) + (F2 - F2*)/(2g);
+// A(F) = -xi_j (Phi_{s+1/2} - Phi_{s-1/2}) / dz, the difference in binary64.
+template <typename Tf, int RUN>
+__device__ __forceinline__ void explicit_run(const InstDesc& d, int v, int s0, int mode) {
     Tf* f = (Tf*)d.f;
     Tf* F2 = (Tf*)d.f2;
-    const double dt = d.dt, g = kImexG;
-    const size_t i = (size_t)v * d.pitch + s;
-    if (mode == 0) {
-        const Tf* F1 = (const Tf*)d.f1;
-        const double fn = (double)f[i], f1 = (double)F1[i];
-        const double a1 = advection(d, F1, v, s);
-        const double fs2 = fn + dt * a1 + (1.0 - 2.0 * g) / g * (f1 - fn);
-        F2[i] = (Tf)fs2;
-        f[i] = (Tf)(fn + 0.5 * dt * a1 + (f1 - fn - fs2) / (2.0 * g));
-    } else {
-        const double a2 = advection(d, (const Tf*)F2, v, s);
-        const Tf o = (Tf)((double)f[i] + 0.5 * dt * a2 + (double)F2[i] / (2.0 * g));
-        if (!isfinite(o)) atomicOr(d.status, 2u);
-        f[i] = o;
+    const double dt = d.dt, g = kImexG, x = d.tab.xv[v];
+    const Tf* A = mode == 0 ? (const Tf*)d.f1 : (const Tf*)F2;   // the field advected
+    Tf ph[RUN + 1];
+#pragma unroll
+    for (int q = 0; q <= RUN; ++q) ph[q] = (Tf)0;
+    if (x != 0.0) run_fluxes<Tf, RUN>(d, A, v, s0, x, ph);
+    unsigned bad = 0;
+#pragma unroll
+    for (int c = 0; c < RUN; ++c) {
+        const int s = s0 + c;
+        if (s >= d.nz) break;
+        const size_t i = (size_t)v * d.pitch + s;
+        const double a = -x * ((double)ph[c + 1] - (double)ph[c]) * d.dz_inv;
+        if (mode == 0) {
+            const double fn = (double)f[i], f1 = (double)A[i];
+            const double fs2 = fn + dt * a + (1.0 - 2.0 * g) / g * (f1 - fn);
+            F2[i] = (Tf)fs2;
+            f[i] = (Tf)(fn + 0.5 * dt * a + (f1 - fn - fs2) / (2.0 * g));
+        } else {
+            const Tf o = (Tf)((double)f[i] + 0.5 * dt * a + (double)A[i] / (2.0 * g));
+            if (!isfinite(o)) bad = 2u;
+            f[i] = o;
+        }
     }
+    if (bad) atomicOr(d.status, bad);
 }
 
-// One thread per (cell, velocity v = blockIdx.y).
+// One thread per cell and velocity v = blockIdx.y.
 template <typename Tf>
 __global__ void __launch_bounds__(kImexThreads) imex_explicit_kernel(InstDesc d, int mode) {
     const int s = blockIdx.x * kImexThreads + threadIdx.x;
-    if (s < d.nz) explicit_point<Tf>(d, blockIdx.y, s, mode);
+    if (s < d.nz) explicit_run<Tf, 1>(d, blockIdx.y, s, mode);
 }
 
-// Batch form: item (instance, first of 64 cells); velocities v = blockIdx.y,
-// blockIdx.y + kImexVY, ...
+// Batch form: item (instance, first cell of kImexThreads runs); velocities
+// v = blockIdx.y, blockIdx.y + kImexVY, ...
 constexpr int kImexVY = 8;
 
 template <typename Tf>
@@ -358,11 +371,10 @@ __global__ void __launch_bounds__(kImexThreads) imex_explicit_batch_kernel(const
     const int2 it = items[blockIdx.x];
     InstDesc d = descs[it.x];
     rebase(d, fbase, wbase);
-    const int s = it.y + threadIdx.x;
-    if (s >= d.nz) return;
-    for (int v = blockIdx.y; v < d.V; v += kImexVY) explicit_point<Tf>(d, v, s, mode);
+    const int s0 = it.y + threadIdx.x * kImexRun;
+    if (s0 >= d.nz) return;
+    for (int v = blockIdx.y; v < d.V; v += kImexVY) explicit_run<Tf, kImexRun>(d, v, s0, mode);
 }
-
 
 // Lanes per cell (L) and angular nodes per lane (JM) of each class.  A single
 // instance spreads a cell over enough lanes to cover its angular nodes (at
@@ -470,6 +482,8 @@ int imex_class(int Q) {
 }
 
 int imex_cells_per_item(int Q) { return kImexBatchThreads / kImexBatchL[imex_class(Q)]; }
+
+int imex_cells_per_explicit_item() { return kImexThreads * kImexRun; }
 
 int launch_imex_steps(const InstDesc& d, int dtype, int nsteps, hipStream_t s) {
     return dtype == RSL_F64 ? imex_steps_t<double>(d, nsteps, s) : imex_steps_t<float>(d, nsteps, s);
