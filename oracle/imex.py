@@ -78,6 +78,9 @@ def implicit_stage(S, F, h):
         with warnings.catch_warnings():        # MINPACK reports when it is at the rounding floor
             warnings.simplefilter("ignore", RuntimeWarning)
             X = fsolve(res, [M[1, s], M[4, s]], xtol=1e-14)
+        r = res(X)
+        if not (abs(r[0]) < 1e-10 and abs(r[1]) < 1e-10):     # the stage's defining equation must hold
+            raise FloatingPointError("oracle: implicit stage of cell %d did not converge (%r)" % (s, r))
         G[:, s] = relaxed(S, F[:, s], M[:, s], X, h)
     return G
 
