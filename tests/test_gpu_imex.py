@@ -51,6 +51,7 @@ CASES = [
     (2, 6, 2, 70, "eq", "inf", 0.0, 0.0, 0.5, 3, "moving"),           # collisionless
     (3, 20, 5, 97, "eq", "const", 1e-4, 0.0, 0.5, 3, "sod"),          # 32 lanes per cell
     (2, 100, 4, 70, "outflow", "const", 0.01, 0.0, 0.5, 2, "moving"), # two nodes per lane
+    (2, 200, 4, 20, "eq", "const", 1e-5, 0.0, 0.5, 2, "sod"),         # four nodes per lane
 ]
 
 
@@ -209,12 +210,13 @@ BATCH = [  # QL, Q, NOm, nz, bc, tau_r, dtype
     (3, 20, 5, 97, "eq", 1e-4, "f64"),
     (2, 100, 4, 64, "outflow", 0.01, "f64"),
     (3, 64, 4, 203, "outflow", 1e-5, "f64"),
+    (2, 200, 4, 20, "eq", 1e-3, "f64"),
 ]
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_batch_imex_matches_oracle(rsl, dtype, tol):
-    """An uneven batch (5 velocity-set classes, ragged tails, a 5-cell tube,
+    """An uneven batch (6 velocity-set classes, ragged tails, a 5-cell tube,
     dt / tau up to 3e4) created with RSL_FLAG_IMEX at dt = 0.5 dz for every
     instance: each instance after two batch steps against two oracle steps,
     and against the single-instance call."""
