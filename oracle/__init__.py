@@ -9,7 +9,10 @@ contraction); ``quadrature.py`` the velocity-set tables; the analytic and
 semi-analytic references the paper compares against live in ``riemann.py`` and
 ``bjorken_ref.py``; the field diagnostics (window integrals, the Sod error
 measure, the Bjorken L2 norm) in ``diagnostics.py``; the reference network of
-the learned correction in ``mlp.py``.  This module wraps ``rslo.c`` with ctypes.
+the learned correction and the moment-preserving feedback into f in
+``mlp.py``; the velocity sets with azimuthal nodes in ``vel3d.py``; the
+implicit-explicit step in ``imex.py``.  This module wraps ``rslo.c`` with
+ctypes.
 
 Parity status per function (pins in tests/test_oracle_*.py):
   quadrature, K^L, K^P ........ pinned (exactness, Table I, calculus identities)
@@ -28,6 +31,14 @@ Parity status per function (pins in tests/test_oracle_*.py):
                                 against a near-inviscid kinetic solve)
   reference network ........... pinned (finite-difference gradients, Adam on a
                                 quadratic, feature definitions)
+  feedback into f, projection . pinned (only T^{mu nu} or only N^mu moved, equilibria
+                                projected onto equilibria, conserved moments kept)
+  azimuthal velocity sets ..... pinned (angular rule exact below its degree, ideal-gas
+                                moments, the aligned set along z, rotation, isotropy
+                                at rest, the 3D frame of boosted and noisy states)
+  IMEX step ................... pinned (stage equation and conserved moments, uniform
+                                state, exact Riemann plateau at dt >> tau, 2nd order,
+                                collisionless = Heun, binary32 storage rounding)
 """
 import ctypes
 import os
