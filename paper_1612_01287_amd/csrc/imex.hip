@@ -180,11 +180,12 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
     // Broyden's method: a finite-difference Jacobian of R(X) = (relaxed
     // moments - X) from the first three evaluations (X, X + e0, X + e1), then
     // steps with rank-one updates after each step above 1e-10 of the scales;
-    // one more step once a step is at 1e-13 of them.  One evaluation site
-    // (frame, K-series, relaxed moments) serves all phases.
+    // the X a step of at most 1e-13 of them reaches is the solution (the next
+    // step would be far smaller still).  One evaluation site (frame,
+    // K-series, relaxed moments) serves all phases.
     const double e0 = 1e-7 * sc[0], e1 = 1e-7 * sc[1];
     Frame fr;
-    bool ok = true, conv = false, last = false;
+    bool ok = true, conv = false;
     double R[2] = {0.0, 0.0}, J[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, r0[2] = {0.0, 0.0}, st[2] = {0.0, 0.0};
     for (int it = 0; it < 43 && ok && !conv; ++it) {
         const int phase = it < 3 ? it : 3;
@@ -202,7 +203,10 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
             xe1 = X[1];
         }
         if (!frame_of(d, M[0], xe0, M[2], M[3], xe1, ser, thr, fr)) { ok = false; break; }
-        if (phase == 3 && last) { conv = true; break; }      // fr is the frame of the final X
+        if (phase == 3 && fabs(st[0]) <= 1e-13 * sc[0] && fabs(st[1]) <= 1e-13 * sc[1]) {
+            conv = true;                                      // fr is the frame of the final X
+            break;
+        }
         double rn[2];
         relaxed_moments<L, JM>(d, nd, Pm, r, fr, h, rn);
         if (phase == 0) {
@@ -217,7 +221,6 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
             J[0][1] = (rn[0] - r0[0]) / e1;
             J[1][1] = (rn[1] - r0[1]) / e1 - 1.0;
         } else {
-            last = fabs(st[0]) <= 1e-13 * sc[0] && fabs(st[1]) <= 1e-13 * sc[1];
             const double y0 = rn[0] - X[0] - R[0], y1 = rn[1] - X[1] - R[1];
             R[0] = rn[0] - X[0];
             R[1] = rn[1] - X[1];
