@@ -157,7 +157,8 @@ __device__ __forceinline__ const double* stage_tables(const InstDesc& d, ImexLds
 // group reads its cell's column before it writes any of it.
 template <typename Tf, int L, int JM>
 __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, Tf* G, double h, int s_first,
-                                               const double* ser, const double* thr, const double* Pm) {
+                                               const double* ser, const double* thr, const double* Pm,
+                                               double* jac, int reuse) {
     const int r = threadIdx.x % L;
     const int s0 = s_first + threadIdx.x / L;
     const bool live = s0 < d.nz;
@@ -177,33 +178,56 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
     for (int i = 0; i < 5; ++i) M[i] = group_sum<L>(M[i]);
     double X[2] = {M[1], M[4]};
     const double sc[2] = {fabs(M[0]), fabs(M[2])};   // scales of the two unknowns
-    // Broyden's method: a finite-difference Jacobian of R(X) = (relaxed
-    // moments - X) from the first three evaluations (X, X + e0, X + e1), then
-    // steps with rank-one updates after each step above 1e-10 of the scales;
-    // the X a step of at most 1e-13 of them reaches is the solution (the next
-    // step would be far smaller still).  One evaluation site (frame,
-    // K-series, relaxed moments) serves all phases.
+    // Broyden's method.  The Jacobian of R(X) = (relaxed moments - X) comes
+    // from finite differences (evaluations at X, X + e0, X + e1) or, with
+    // reuse, from the cell's previous solve in this call (kept in the work
+    // buffer's per-cell rows: the states of consecutive stages are close);
+    // rank-one updates after each step above 1e-10 of the scales.  The X that
+    // a step of at most 1e-13 of them reaches is the solution (the next step
+    // would be far smaller still), provided the residual before that step is
+    // below 1e-9 of the scales (a carried Jacobian far off cannot pass for
+    // convergence); a carried Jacobian that is singular or needs more than 12
+    // steps is replaced by finite differences at the current X.  One
+    // evaluation site (frame, K-series, relaxed moments) serves all phases.
     const double e0 = 1e-7 * sc[0], e1 = 1e-7 * sc[1];
     Frame fr;
-    bool ok = true, conv = false;
+    bool ok = true, conv = false, fresh = !reuse;
     double R[2] = {0.0, 0.0}, J[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, r0[2] = {0.0, 0.0}, st[2] = {0.0, 0.0};
-    for (int it = 0; it < 43 && ok && !conv; ++it) {
-        const int phase = it < 3 ? it : 3;
+    int phase = 0, nst = 0;        // phases 0-2: finite differences; 4: residual only; 3: steps
+    if (reuse) {
+        J[0][0] = jac[s];
+        J[0][1] = jac[(size_t)d.pitch + s];
+        J[1][0] = jac[2 * (size_t)d.pitch + s];
+        J[1][1] = jac[3 * (size_t)d.pitch + s];
+        phase = 4;
+    }
+    for (int it = 0; it < 48 && ok && !conv; ++it) {
+        if (phase == 3 && !fresh && nst >= 12) {
+            phase = 0;
+            fresh = true;
+        }
         double xe0 = X[0], xe1 = X[1];
         if (phase == 1) xe0 += e0;
         if (phase == 2) xe1 += e1;
         if (phase == 3) {
             const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-            if (!(fabs(det) > 0.0)) { ok = false; break; }
+            if (!(fabs(det) > 0.0)) {
+                if (fresh) { ok = false; break; }
+                phase = 0;
+                fresh = true;
+                continue;
+            }
             st[0] = -(J[1][1] * R[0] - J[0][1] * R[1]) / det;
             st[1] = -(J[0][0] * R[1] - J[1][0] * R[0]) / det;
             X[0] += st[0];
             X[1] += st[1];
             xe0 = X[0];
             xe1 = X[1];
+            ++nst;
         }
         if (!frame_of(d, M[0], xe0, M[2], M[3], xe1, ser, thr, fr)) { ok = false; break; }
-        if (phase == 3 && fabs(st[0]) <= 1e-13 * sc[0] && fabs(st[1]) <= 1e-13 * sc[1]) {
+        if (phase == 3 && fabs(st[0]) <= 1e-13 * sc[0] && fabs(st[1]) <= 1e-13 * sc[1] &&
+            fabs(R[0]) <= 1e-9 * sc[0] && fabs(R[1]) <= 1e-9 * sc[1]) {
             conv = true;                                      // fr is the frame of the final X
             break;
         }
@@ -214,12 +238,21 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
             r0[1] = rn[1];
             R[0] = rn[0] - X[0];
             R[1] = rn[1] - X[1];
+            phase = 1;
         } else if (phase == 1) {
             J[0][0] = (rn[0] - r0[0]) / e0 - 1.0;
             J[1][0] = (rn[1] - r0[1]) / e0;
+            phase = 2;
         } else if (phase == 2) {
             J[0][1] = (rn[0] - r0[0]) / e1;
             J[1][1] = (rn[1] - r0[1]) / e1 - 1.0;
+            phase = 3;
+            nst = 0;
+        } else if (phase == 4) {
+            R[0] = rn[0] - X[0];
+            R[1] = rn[1] - X[1];
+            phase = 3;
+            nst = 0;
         } else {
             const double y0 = rn[0] - X[0] - R[0], y1 = rn[1] - X[1] - R[1];
             R[0] = rn[0] - X[0];
@@ -235,6 +268,12 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
             J[1][0] += u1 * st[0];
             J[1][1] += u1 * st[1];
         }
+    }
+    if (live && ok && conv && r == 0) {           // the Jacobian for this cell's next solve
+        jac[s] = J[0][0];
+        jac[(size_t)d.pitch + s] = J[0][1];
+        jac[2 * (size_t)d.pitch + s] = J[1][0];
+        jac[3 * (size_t)d.pitch + s] = J[1][1];
     }
     if (!live) return;
     if (!ok || !conv) {
@@ -264,10 +303,11 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
 }
 
 template <typename Tf, int L, int JM>
-__global__ void __launch_bounds__(kImexThreads) imex_implicit_kernel(InstDesc d, const Tf* Fs, Tf* G, double h) {
+__global__ void __launch_bounds__(kImexThreads) imex_implicit_kernel(InstDesc d, const Tf* Fs, Tf* G, double h,
+                                                                      int reuse) {
     __shared__ ImexLds t;
     const double* Pm = stage_tables(d, t);
-    implicit_cells<Tf, L, JM>(d, Fs, G, h, blockIdx.x * (kImexThreads / L), t.ser, t.thr, Pm);
+    implicit_cells<Tf, L, JM>(d, Fs, G, h, blockIdx.x * (kImexThreads / L), t.ser, t.thr, Pm, d.cell, reuse);
 }
 
 // Batch form: item (instance, first cell); second = 0 solves F1 from f,
@@ -277,7 +317,8 @@ __global__ void __launch_bounds__(kImexThreads) imex_implicit_kernel(InstDesc d,
 template <typename Tf, int L, int JM>
 __global__ void __launch_bounds__(kImexBatchThreads, JM == 1 ? 3 : 1) imex_implicit_batch_kernel(const InstDesc* __restrict__ descs,
                                                                             const int2* __restrict__ items,
-                                                                            char* fbase, char* wbase, int second) {
+                                                                            char* fbase, char* wbase, int second,
+                                                                            int reuse) {
     const int2 it = items[blockIdx.x];
     InstDesc d = descs[it.x];
     rebase(d, fbase, wbase);
@@ -285,7 +326,7 @@ __global__ void __launch_bounds__(kImexBatchThreads, JM == 1 ? 3 : 1) imex_impli
     const double* Pm = stage_tables(d, t);
     const Tf* F = (const Tf*)(second ? d.f2 : d.f);
     Tf* G = (Tf*)(second ? d.f2 : d.f1);
-    implicit_cells<Tf, L, JM>(d, F, G, kImexG * d.dt, it.y, t.ser, t.thr, Pm);
+    implicit_cells<Tf, L, JM>(d, F, G, kImexG * d.dt, it.y, t.ser, t.thr, Pm, d.cell, reuse);
 }
 
 // Population of velocity v at cell c (ghosts per the instance's rule).
@@ -394,16 +435,16 @@ struct ImexClass;
 #define RSL_IMEX_CLASS(C, L, JM, LB, JMB)                                                                     \
     template <typename Tf>                                                                                    \
     struct ImexClass<Tf, C> {                                                                                 \
-        static void single(const InstDesc& d, const Tf* F, Tf* G, double h, hipStream_t s) {                 \
+        static void single(const InstDesc& d, const Tf* F, Tf* G, double h, int reuse, hipStream_t s) {      \
             const int cells = kImexThreads / L;                                                               \
             hipLaunchKernelGGL((imex_implicit_kernel<Tf, L, JM>), dim3((d.nz + cells - 1) / cells),           \
-                               dim3(kImexThreads), 0, s, d, F, G, h);                                         \
+                               dim3(kImexThreads), 0, s, d, F, G, h, reuse);                                  \
         }                                                                                                     \
         static void batch(const InstDesc* descs, const int2* items, int n, char* fb, char* wb, int second,    \
-                          hipStream_t s) {                                                                    \
+                          int reuse, hipStream_t s) {                                                         \
             static_assert(LB == kImexBatchL[C], "batch lanes per cell");                                      \
             hipLaunchKernelGGL((imex_implicit_batch_kernel<Tf, LB, JMB>), dim3(n), dim3(kImexBatchThreads), 0, \
-                               s, descs, items, fb, wb, second);                                              \
+                               s, descs, items, fb, wb, second, reuse);                                       \
         }                                                                                                     \
     };
 //              class  single    batch      angular nodes
@@ -419,33 +460,33 @@ RSL_IMEX_CLASS(8, 64, 16, 64, 16) // <= 1024
 #undef RSL_IMEX_CLASS
 
 template <typename Tf>
-void implicit_single(int c, const InstDesc& d, const Tf* F, Tf* G, double h, hipStream_t s) {
+void implicit_single(int c, const InstDesc& d, const Tf* F, Tf* G, double h, int reuse, hipStream_t s) {
     switch (c) {
-        case 0: ImexClass<Tf, 0>::single(d, F, G, h, s); break;
-        case 1: ImexClass<Tf, 1>::single(d, F, G, h, s); break;
-        case 2: ImexClass<Tf, 2>::single(d, F, G, h, s); break;
-        case 3: ImexClass<Tf, 3>::single(d, F, G, h, s); break;
-        case 4: ImexClass<Tf, 4>::single(d, F, G, h, s); break;
-        case 5: ImexClass<Tf, 5>::single(d, F, G, h, s); break;
-        case 6: ImexClass<Tf, 6>::single(d, F, G, h, s); break;
-        case 7: ImexClass<Tf, 7>::single(d, F, G, h, s); break;
-        default: ImexClass<Tf, 8>::single(d, F, G, h, s); break;
+        case 0: ImexClass<Tf, 0>::single(d, F, G, h, reuse, s); break;
+        case 1: ImexClass<Tf, 1>::single(d, F, G, h, reuse, s); break;
+        case 2: ImexClass<Tf, 2>::single(d, F, G, h, reuse, s); break;
+        case 3: ImexClass<Tf, 3>::single(d, F, G, h, reuse, s); break;
+        case 4: ImexClass<Tf, 4>::single(d, F, G, h, reuse, s); break;
+        case 5: ImexClass<Tf, 5>::single(d, F, G, h, reuse, s); break;
+        case 6: ImexClass<Tf, 6>::single(d, F, G, h, reuse, s); break;
+        case 7: ImexClass<Tf, 7>::single(d, F, G, h, reuse, s); break;
+        default: ImexClass<Tf, 8>::single(d, F, G, h, reuse, s); break;
     }
 }
 
 template <typename Tf>
-void implicit_batch(int c, const InstDesc* descs, const int2* items, int n, char* fb, char* wb, int second,
+void implicit_batch(int c, const InstDesc* descs, const int2* items, int n, char* fb, char* wb, int second, int reuse,
                     hipStream_t s) {
     switch (c) {
-        case 0: ImexClass<Tf, 0>::batch(descs, items, n, fb, wb, second, s); break;
-        case 1: ImexClass<Tf, 1>::batch(descs, items, n, fb, wb, second, s); break;
-        case 2: ImexClass<Tf, 2>::batch(descs, items, n, fb, wb, second, s); break;
-        case 3: ImexClass<Tf, 3>::batch(descs, items, n, fb, wb, second, s); break;
-        case 4: ImexClass<Tf, 4>::batch(descs, items, n, fb, wb, second, s); break;
-        case 5: ImexClass<Tf, 5>::batch(descs, items, n, fb, wb, second, s); break;
-        case 6: ImexClass<Tf, 6>::batch(descs, items, n, fb, wb, second, s); break;
-        case 7: ImexClass<Tf, 7>::batch(descs, items, n, fb, wb, second, s); break;
-        default: ImexClass<Tf, 8>::batch(descs, items, n, fb, wb, second, s); break;
+        case 0: ImexClass<Tf, 0>::batch(descs, items, n, fb, wb, second, reuse, s); break;
+        case 1: ImexClass<Tf, 1>::batch(descs, items, n, fb, wb, second, reuse, s); break;
+        case 2: ImexClass<Tf, 2>::batch(descs, items, n, fb, wb, second, reuse, s); break;
+        case 3: ImexClass<Tf, 3>::batch(descs, items, n, fb, wb, second, reuse, s); break;
+        case 4: ImexClass<Tf, 4>::batch(descs, items, n, fb, wb, second, reuse, s); break;
+        case 5: ImexClass<Tf, 5>::batch(descs, items, n, fb, wb, second, reuse, s); break;
+        case 6: ImexClass<Tf, 6>::batch(descs, items, n, fb, wb, second, reuse, s); break;
+        case 7: ImexClass<Tf, 7>::batch(descs, items, n, fb, wb, second, reuse, s); break;
+        default: ImexClass<Tf, 8>::batch(descs, items, n, fb, wb, second, reuse, s); break;
     }
 }
 
@@ -455,9 +496,9 @@ int imex_steps_t(const InstDesc& d, int nsteps, hipStream_t s) {
     const double h = kImexG * d.dt;
     const int c = imex_class(d.Q);
     for (int it = 0; it < nsteps; ++it) {
-        implicit_single<Tf>(c, d, (const Tf*)d.f, (Tf*)d.f1, h, s);
+        implicit_single<Tf>(c, d, (const Tf*)d.f, (Tf*)d.f1, h, it > 0, s);   // fresh Jacobians first
         hipLaunchKernelGGL(imex_explicit_kernel<Tf>, gx, dim3(kImexThreads), 0, s, d, 0);
-        implicit_single<Tf>(c, d, (const Tf*)d.f2, (Tf*)d.f2, h, s);
+        implicit_single<Tf>(c, d, (const Tf*)d.f2, (Tf*)d.f2, h, 1, s);
         hipLaunchKernelGGL(imex_explicit_kernel<Tf>, gx, dim3(kImexThreads), 0, s, d, 1);
     }
     return hip_check(hipGetLastError(), "imex step launch");
@@ -469,7 +510,7 @@ int imex_batch_steps_t(const InstDesc* descs, const ImexItems& it, char* fb, cha
     for (int step = 0; step < nsteps; ++step) {
         for (int second = 0; second < 2; ++second) {
             for (int c = 0; c < kImexClasses; ++c)
-                if (it.n[c]) implicit_batch<Tf>(c, descs, it.items[c], it.n[c], fb, wb, second, s);
+                if (it.n[c]) implicit_batch<Tf>(c, descs, it.items[c], it.n[c], fb, wb, second, step > 0 || second, s);
             if (it.nx) hipLaunchKernelGGL(imex_explicit_batch_kernel<Tf>, gx, dim3(kImexThreads), 0, s, descs, it.x,
                                           fb, wb, second);
         }
