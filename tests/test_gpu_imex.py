@@ -320,3 +320,23 @@ def test_imex_second_order_at_size(rsl):
         errs.append(np.max(np.abs(inst.f().cpu().numpy() - want)))
     p1, p2 = np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])
     assert 1.7 < p1 < 2.5 and 1.7 < p2 < 2.5, (errs, p1, p2)
+
+
+@pytest.mark.parametrize("tau_r,bc", [(1e-7, "eq"), (2e-3, "outflow")])
+def test_imex_steps_in_one_call_match_single_steps(rsl, tau_r, bc):
+    """Within one call the implicit solves start from each cell's previous
+    Jacobian; the first solve of a call starts from finite differences.  The
+    converged stages are the same: eight steps in one call against eight
+    calls of one step, and against the oracle's eight steps."""
+    nz = 150
+    quad, inst, vs, T = _pair(rsl, 3, 8, 4, nz, bc, "const", tau_r, 0.0, inputs.SOD_PAPER)
+    one = rsl.Instance(quad, inst.p)
+    inst.init()
+    one.init()
+    dt = 0.5 / nz
+    inst.step_imex(dt, 8)
+    for _ in range(8):
+        one.step_imex(dt, 1)
+    a, b = inst.f().cpu().numpy(), one.f().cpu().numpy()
+    assert _rel(a, b) < 1e-12
+    assert _rel(a, T.run(T.init(), dt, 8)) < 1e-11
