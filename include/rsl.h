@@ -172,8 +172,10 @@ int rsl_step(const rsl_quad* q, const rsl_problem* p, void* f_dev, void* work_de
  *   F1 = f + g dt Q(F1),  F2 = f + dt A(F1) + (1 - 2g) dt Q(F1) + g dt Q(F2),
  *   f' = f + dt/2 (A(F1) + A(F2)) + dt/2 (Q(F1) + Q(F2)).
  * Each implicit stage is solved per cell: the collision keeps N^0, T^00,
- * T^0z, and Broyden's method (from a finite-difference Jacobian) finds the
- * N^z, T^zz whose Landau frame, tau and f^eq reproduce them.  Binary64 or
+ * T^0z, and Broyden's method finds the N^z, T^zz whose Landau frame, tau
+ * and f^eq reproduce them (its Jacobian from finite differences in the first
+ * stage of a call, then carried per cell from stage to stage in the work
+ * buffer's per-cell rows).  Binary64 or
  * binary32 storage (f and the stages stored in the instance's dtype; the
  * arithmetic in binary64 except the WENO5 stencil of binary32 storage, which
  * takes binary32 weights as rsl_step does).  Uses the work buffer of rsl_sizes after rsl_init
