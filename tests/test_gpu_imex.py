@@ -340,3 +340,24 @@ def test_imex_steps_in_one_call_match_single_steps(rsl, tau_r, bc):
     a, b = inst.f().cpu().numpy(), one.f().cpu().numpy()
     assert _rel(a, b) < 1e-12
     assert _rel(a, T.run(T.init(), dt, 8)) < 1e-11
+
+
+def test_explicit_and_imex_steps_alternate(rsl):
+    """rsl_step and rsl_step_imex share the work buffer's per-cell rows (the
+    explicit stages' coefficients, the implicit solves' carried Jacobians);
+    each call sets the rows it reads, so the two alternate freely: explicit,
+    IMEX and explicit steps against the oracle's same sequence."""
+    nz = 130
+    quad, inst, vs, T = _pair(rsl, 3, 8, 4, nz, "outflow", "const", 0.05, 0.0, inputs.SOD_C1)
+    S = oracle.Sod(vs, nz, tau_mode=oracle.TAU_CONST, tau_r=0.05, bc=oracle.BC_OUTFLOW, **inputs.SOD_C1)
+    inst.init()
+    dt = 0.5 / nz
+    f = S.init()
+    for kind in ("rk3", "imex", "imex", "rk3", "imex"):
+        if kind == "rk3":
+            inst.step(dt, 2)
+            f = S.run(f, dt, 2)
+        else:
+            inst.step_imex(dt, 2)
+            f = T.run(f, dt, 2)
+        assert _rel(inst.f().cpu().numpy(), f) < 1e-11, kind
