@@ -687,7 +687,7 @@ def copy_calibration(torch):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: the multi-GPU path is not built (one GPU per box)",
+        print("bench.py runs on one GPU only: the multi-GPU path (z slabs or instances per GPU) is not built",
               file=sys.stderr)
         sys.exit(2)
     import torch
