@@ -45,9 +45,13 @@ struct Frame {
     double c0[kMaxNOm + 1], c1[kMaxNOm + 1];
 };
 
+// nt: the series length of the cell's previous evaluation (0: none), kept
+// when it is still the first length whose threshold covers beta^2 (the
+// binary search's answer; consecutive evaluations of a solve barely move
+// beta), else searched.
 template <typename TP>
-__device__ __forceinline__ bool frame_of(const InstDesc& d, double N0, double Nz, double T00, double T0z, double Tzz, TP ser,
-                         TP thr, Frame& fr) {
+__device__ __forceinline__ bool frame_of(const InstDesc& d, double N0, double Nz, double T00, double T0z, double Tzz,
+                                         TP ser, TP thr, Frame& fr, int& nt) {
     fr.cs = landau(N0, Nz, T00, T0z, Tzz);
     if (!fr.cs.ok) return false;
     const CellState& cs = fr.cs;
@@ -55,7 +59,9 @@ __device__ __forceinline__ bool frame_of(const InstDesc& d, double N0, double Nz
     if (d.tau_mode == RSL_TAU_ETAS)
         tau = d.tau_aw0 / cs.T * (1.0 - 0.25 * log(cs.n / (cs.T * cs.T * cs.T) * d.lambda_ref));
     fr.rate = d.tau_mode == RSL_TAU_INF ? 0.0 : cs.gamma / tau;
-    const int nt = series_terms_uniform(fmin(cs.beta * cs.beta, d.beta_series * d.beta_series), thr);
+    const double x = fmin(cs.beta * cs.beta, d.beta_series * d.beta_series);
+    const bool keep = nt > 0 && (nt == 1 || x > thr[nt - 1]) && (nt == kSeriesTerms || x <= thr[nt]);
+    if (!keep) nt = series_terms_uniform(x, thr);
     feq_coef(cs.n, cs.T, cs.beta, cs.gamma, d.T0, d.NOm, d.beta_series, ser, nt, fr.c0, fr.c1);
     return true;
 }
@@ -194,6 +200,7 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
     bool ok = true, conv = false, fresh = !reuse;
     double R[2] = {0.0, 0.0}, J[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, r0[2] = {0.0, 0.0}, st[2] = {0.0, 0.0};
     int phase = 0, nst = 0;        // phases 0-2: finite differences; 4: residual only; 3: steps
+    int nt_cell = 0;               // series length of the cell's last frame
     if (reuse) {
         J[0][0] = jac[s];
         J[0][1] = jac[(size_t)d.pitch + s];
@@ -225,7 +232,7 @@ __device__ __forceinline__ void implicit_cells(const InstDesc& d, const Tf* Fs, 
             xe1 = X[1];
             ++nst;
         }
-        if (!frame_of(d, M[0], xe0, M[2], M[3], xe1, ser, thr, fr)) { ok = false; break; }
+        if (!frame_of(d, M[0], xe0, M[2], M[3], xe1, ser, thr, fr, nt_cell)) { ok = false; break; }
         if (phase == 3 && fabs(st[0]) <= 1e-13 * sc[0] && fabs(st[1]) <= 1e-13 * sc[1] &&
             fabs(R[0]) <= 1e-9 * sc[0] && fabs(R[1]) <= 1e-9 * sc[1]) {
             conv = true;                                      // fr is the frame of the final X
